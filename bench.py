@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark: macro-particle-turns/s of the plain FP64 GPU tracker on one MI355X.
+
+Workload (default): the current-scan configuration -- eight single-bunch jobs
+of 1e6 macro-particles each (bunch currents 0.1-5 mA), 3rd-harmonic cavity at
+90% of its flat-potential voltage, broadband-resonator wake on 512 bins,
+run as one launch set per turn.  A step is one turn of the whole hot path
+(between-turn kernel: moments, wake potential; push kernel: kick, damping,
+noise, drift, histogram, deposits, moment sums; moment output).  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line with the throughput, the push kernel's roofline figures
+(algorithmic bytes per launch / average launch duration from HIP events over
+the timed region) and the oracle timed on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, vendor figure
+BYTES_PER_PARTICLE_TURN = 32  # read tau, delta + write tau, delta (FP64)
+PMC_FILE = os.path.join(ROOT, "profiles", "push_c2_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1809_00391_amd", "csrc", "mbt_kernels.hip")
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(particles_per_launch):
+    """HBM bytes per push launch from committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size), or
+    None when they are missing or were taken on a different kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    d = json.load(open(PMC_FILE))
+    if d.get("kernel_sha") != kernel_sha() or d.get("particles_per_launch") != particles_per_launch:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def make_tracker(w):
+    from paper_1809_00391_amd import tracker as tr
+    t = tr.Tracker(w.ring)
+    if w.hc_flat:
+        t.set_harmonic_cavity(tr.hc_flat_fraction(w.ring, *w.hc_flat))
+    t.set_fill(w.buckets, w.currents_A, w.streams)
+    if w.grid is not None:
+        t.set_short_range(list(w.short_range), w.grid)
+    if w.long_range:
+        t.set_long_range(list(w.long_range))
+    t.bind(w.N)
+    t.init_gaussian(w.sigma_tau0, w.sigma_delta0, w.seed)
+    return t
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle (as it stands) on this host's cores, on a bounded number of
+    turns of the same workload."""
+    from oracle import ref
+    s = ref.RefSim(w.ring)
+    if w.hc_flat:
+        s.set_harmonic_cavity(ref.hc_flat_fraction(w.ring, *w.hc_flat))
+    s.set_fill(w.buckets, w.currents_A, w.streams)
+    if w.grid is not None:
+        s.set_short_range(list(w.short_range), w.grid)
+    if w.long_range:
+        s.set_long_range(list(w.long_range))
+    s.init_gaussian(w.N, w.sigma_tau0, w.sigma_delta0, w.seed)
+    t0 = time.perf_counter()
+    s.track(2)
+    per_turn = (time.perf_counter() - t0) / 2
+    turns = int(max(3, min(1000, budget_s / max(per_turn, 1e-9))))
+    t0 = time.perf_counter()
+    s.track(turns)
+    dt = time.perf_counter() - t0
+    return {"value": w.M * w.N * turns / dt, "unit": "macro-particle-turns/s",
+            "cores": ref.threads(), "kind": "oracle",
+            "sample": f"{turns} turns of the same workload ({w.M} x {w.N} particles) after 2 "
+                      f"warm-up turns, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000, help="timed turns")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed turns first")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="bracket every k-th push launch with HIP events")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle time for the CPU baseline (0: skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the tracker is a "
+              "single-GPU library; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1809_00391_amd import workloads as wl
+
+    w = wl.PRESETS[args.workload]
+    torch.cuda.set_device(0)
+    t = make_tracker(w)
+    stream = t.stream
+    with torch.cuda.stream(stream):
+        if args.copy_probe:
+            a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
+        if args.warmup:
+            t.track(args.warmup, moments=True)
+        t.set_timing(args.timing_every)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        ev0.record(stream)
+        mom = t.track(args.steps, moments=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    push_ms, push_n, prep_ms, prep_n = t.get_timing()
+    particles = w.M * w.N
+    value = particles * args.steps / elapsed
+    push_avg_s = push_ms / 1e3 / max(push_n, 1)
+    achieved = BYTES_PER_PARTICLE_TURN * particles / push_avg_s / 1e9
+    traffic = traffic_from_profiles(particles)
+    finite = bool(torch.isfinite(torch.from_numpy(mom[-1])).all())
+
+    out = {
+        "metric": "macro-particle-turns/s (FP64 plain vs batched mixed-prec) at 1 GPU; "
+                  "p50/p99 job lat",
+        "value": value,
+        "unit": "macro-particle-turns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "form": "plain FP64 tracker (one job per launch set, no graphs, no MFMA)",
+            "bunches": w.M, "particles_per_bunch": w.N,
+            "bins": w.grid[0] if w.grid else 0,
+            "long_range_resonators": len(w.long_range),
+            "turns_timed": args.steps,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_push",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "avg_launch_us": push_avg_s * 1e6, "launches_timed": push_n,
+            "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles,
+            "prep_avg_us": prep_ms * 1e3 / max(prep_n, 1),
+        },
+        "moments_finite": finite,
+    }
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,249 @@
+/*
+ * mbt.h -- C ABI of the MI355X longitudinal multi-bunch macro-particle tracker.
+ *
+ * The library advances macro-particles of electron bunches in a storage ring
+ * turn by turn in the longitudinal plane, with the method of Xu, Locans,
+ * Adelmann and Stingelin, "Calculation of Longitudinal Collective
+ * Instabilities with mbtrack-cuda" (arXiv:1809.00391):
+ *   - single-particle map: RF energy gain minus radiated energy (Sec. 2.2,
+ *     Eq. 1), radiation damping and quantum excitation (Eq. 5, delta line),
+ *     drift with the momentum compaction (Eq. 2);
+ *   - optional harmonic cavity (Sec. 2.2, last paragraph);
+ *   - short-range wake: particles binned on a fixed grid, wake potential of
+ *     the binned line density, kick per bin (Sec. 2.3, Eq. 6);
+ *   - long-range resonators acting bunch to bunch (Sec. 4 study of a cavity
+ *     higher-order mode) through one complex phasor per resonator;
+ *   - per-bunch statistics every turn (Sec. 2.4).
+ *
+ * Units: tau in seconds (arrival-time offset from the bucket centre, tau > 0
+ * arrives later), delta = dE/E0, energies in eV, voltages in V, currents in A.
+ * All particle arithmetic is IEEE binary64 on the GPU.
+ *
+ * General conventions
+ *   - Every call returns MBT_OK (0) or a negative MBT_E* code; nothing throws
+ *     or aborts across the ABI.  mbt_last_error() returns the message of the
+ *     last failing call on a context.
+ *   - A context is used by one host thread at a time.
+ *   - Host pointers are borrowed for the duration of the call only; output
+ *     arrays are allocated by the caller with the sizes stated below.
+ *   - Device memory (particle state and workspace) is allocated by the caller
+ *     and handed over with mbt_bind(); the library never allocates device
+ *     memory.  It allocates a small amount of pinned host memory at bind
+ *     time for its asynchronous output copies.
+ *   - Work is enqueued on the caller's HIP stream given to mbt_bind().
+ *   - Call order: mbt_create -> [mbt_set_harmonic_cavity] -> mbt_set_fill ->
+ *     [mbt_set_short_range] -> [mbt_set_long_range] -> mbt_query_bytes ->
+ *     mbt_bind -> (mbt_init_gaussian | mbt_set_particles + mbt_set_state) ->
+ *     mbt_track ...  Out-of-order calls return MBT_ESTATE.
+ */
+#ifndef MBT_H
+#define MBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define MBT_OK 0
+#define MBT_EINVAL (-1)   /* invalid argument                                 */
+#define MBT_ESTATE (-2)   /* call made in the wrong order                     */
+#define MBT_ENOSPC (-3)   /* caller buffer smaller than mbt_query_bytes says  */
+#define MBT_EDEVICE (-4)  /* HIP runtime error; message kept                  */
+#define MBT_ENUMERIC (-5) /* non-finite bunch moment detected                 */
+#define MBT_ENOMEM (-6)   /* host allocation failed                           */
+
+/* Where a particle array lives (mbt_set_particles / mbt_get_particles). */
+#define MBT_HOST 0
+#define MBT_DEVICE 1
+
+/* Limits. */
+#define MBT_MAX_BINS 4096       /* short-range grid bins                     */
+#define MBT_MAX_SHORT_RANGE 16  /* resonators summed into the wake table     */
+#define MBT_MAX_LONG_RANGE 4    /* long-range resonators (phasors)           */
+
+/* Ring and main RF (the lattice parameters of the paper's Table 1 that act in
+ * the longitudinal plane).  T0 = harmonic / f_rf_Hz. */
+typedef struct {
+    double energy_eV;   /* E0 > 0                                             */
+    double f_rf_Hz;     /* main RF frequency > 0                              */
+    double v_rf_V;      /* main RF peak voltage > u0_eV                       */
+    double alpha_c;     /* momentum compaction, nonzero, sign kept            */
+    double u0_eV;       /* energy radiated per turn >= 0 (Eq. 1 U_rad)        */
+    double tau_long_s;  /* longitudinal amplitude damping time > 0; +inf: off */
+    double sigma_delta; /* equilibrium relative energy spread >= 0 (Eq. 5)    */
+    int32_t harmonic;   /* h >= 1                                             */
+} mbt_ring;
+
+/* Harmonic cavity at fixed voltage: adds k*V_rf*sin(n*phi_h - n*w_rf*tau). */
+typedef struct {
+    int32_t n;          /* harmonic of the cavity, >= 2                       */
+    double v_ratio;     /* k = V_hc / V_rf >= 0                               */
+    double phase_n_rad; /* n*phi_h                                            */
+} mbt_hc;
+
+/* Resonator impedance (Sec. 2.3: the total wake is a sum of resonators). */
+typedef struct {
+    double rs_ohm;      /* shunt impedance >= 0                               */
+    double q;           /* quality factor > 0.5                               */
+    double fr_Hz;       /* resonant frequency > 0                             */
+} mbt_resonator;
+
+/* Fixed binning grid relative to the bucket centre (Sec. 2.3): bin k covers
+ * [tau_min + k*D, tau_min + (k+1)*D) with D = (tau_max - tau_min)/nbins; the
+ * index is floor((tau - tau_min) * (nbins / (tau_max - tau_min))). */
+typedef struct {
+    int32_t nbins;      /* 1 .. MBT_MAX_BINS                                  */
+    double tau_min_s;
+    double tau_max_s;   /* > tau_min_s                                        */
+} mbt_grid;
+
+/* Per-bunch statistics after a turn (Sec. 2.4): means and population rms
+ * over all macro-particles of the bunch. */
+typedef struct {
+    double mean_tau;
+    double mean_delta;
+    double rms_tau;
+    double rms_delta;
+} mbt_moments;
+
+typedef struct mbt_ctx mbt_ctx;
+
+/* Message for a return code (static string). */
+const char *mbt_strerror(int code);
+
+/* Message of the last failing call on ctx (never NULL). */
+const char *mbt_last_error(const mbt_ctx *ctx);
+
+/* Create a context for one tracking job on the current HIP device.
+ * Validates the ring (Sec. 2.2, Eqs. 1, 2, 5): MBT_EINVAL if E0 <= 0,
+ * f_rf <= 0, V_rf <= u0, u0 < 0, alpha_c == 0, tau_long <= 0,
+ * sigma_delta < 0, harmonic < 1 or any value is NaN.  The synchronous phase
+ * solves V_rf sin(phi_s) = u0 on the branch with alpha_c cos(phi_s) > 0.
+ * *out receives the context (NULL on failure); free it with mbt_destroy. */
+int mbt_create(const mbt_ring *ring, mbt_ctx **out);
+
+/* Free a context (NULL is allowed).  Does not free caller-owned device
+ * memory; synchronises the bound stream first. */
+void mbt_destroy(mbt_ctx *ctx);
+
+/* Harmonic cavity of order n at frac times the flat-potential voltage, with
+ * the flat-potential phase (total voltage and its first two derivatives match
+ * U0, 0, 0 at tau = 0).  MBT_EINVAL if n < 2, frac <= 0 or no flat-potential
+ * solution exists for this ring. */
+int mbt_hc_flat_fraction(const mbt_ring *ring, int32_t n, double frac, mbt_hc *out);
+
+/* Set (hc != NULL) or remove (hc == NULL) the harmonic cavity (Sec. 2.2) and
+ * re-solve phi_s from V_rf sin(phi_s) + k V_rf sin(n phi_h) = u0.
+ * MBT_EINVAL if no synchronous phase exists; the previous cavity is kept. */
+int mbt_set_harmonic_cavity(mbt_ctx *ctx, const mbt_hc *hc);
+
+/* Filling pattern (Sec. 4): M bunches in buckets bucket[0] < ... < bucket[M-1]
+ * within [0, h), bunch currents current_A[b] >= 0 (bunch charge I_b * T0).
+ * stream (may be NULL) gives each bunch's random-stream ordinal (default b):
+ * the noise of bunch b is keyed by (seed, turn, stream[b], particle), so two
+ * bunches with the same ordinal and seed see the same noise.
+ * Must precede mbt_bind (MBT_ESTATE after it). */
+int mbt_set_fill(mbt_ctx *ctx, int32_t M, const int32_t *bucket, const double *current_A,
+                 const int32_t *stream);
+
+/* Short-range wake (Sec. 2.3, Eq. 6): nres resonators summed into one wake
+ * table sampled at bin distances (self term W(0+)/2), on grid *g.  Particles
+ * outside the grid get no short-range kick.  g == NULL removes the
+ * short-range kick.  MBT_EINVAL on Q <= 0.5, Rs < 0, fr <= 0, nbins outside
+ * [1, MBT_MAX_BINS], tau_min >= tau_max or nres > MBT_MAX_SHORT_RANGE.
+ * Must precede mbt_bind. */
+int mbt_set_short_range(mbt_ctx *ctx, int32_t nres, const mbt_resonator *res,
+                        const mbt_grid *g);
+
+/* Long-range resonators (Sec. 4 higher-order mode): each acts on later
+ * bunch passages through a complex phasor rotated bucket to bucket; its
+ * same-bunch same-turn part acts through the short-range table, to which it
+ * is added when a grid is set.  nres <= MBT_MAX_LONG_RANGE.
+ * Must precede mbt_bind. */
+int mbt_set_long_range(mbt_ctx *ctx, int32_t nres, const mbt_resonator *res);
+
+/* Device bytes the caller must provide for N macro-particles per bunch:
+ * *state_bytes for the particle coordinates (tau and delta, FP64,
+ * bunch-major with rows padded to a multiple of 64 particles) and
+ * *work_bytes for tables, histograms, partial sums and output rings.
+ * MBT_ESTATE if the fill is not set; MBT_EINVAL if N < 1 or N > 2^32. */
+int mbt_query_bytes(const mbt_ctx *ctx, int64_t N, size_t *state_bytes, size_t *work_bytes);
+
+/* Bind caller-owned device memory and a HIP stream (hipStream_t passed as
+ * void*, NULL = default stream).  d_state and d_work must be 256-byte
+ * aligned device pointers of at least the queried sizes (MBT_ENOSPC
+ * otherwise).  Uploads the wake table and per-bunch constants, clears the
+ * workspace.  The caller keeps ownership and must keep the memory alive until
+ * mbt_destroy.  Binding again (e.g. a new N) replaces the previous binding. */
+int mbt_bind(mbt_ctx *ctx, int64_t N, void *d_state, size_t state_bytes, void *d_work,
+             size_t work_bytes, void *hip_stream);
+
+/* Initial distribution: tau ~ N(0, sigma_tau_s), delta ~ N(0, sigma_delta)
+ * per particle from one Box-Muller pair of Philox-4x32-10 with key = seed and
+ * counter = (particle, stream ordinal, 0, 1).  Sets turn = 0, the seed, and
+ * clears the long-range phasors.  Asynchronous on the bound stream. */
+int mbt_init_gaussian(mbt_ctx *ctx, double sigma_tau_s, double sigma_delta, uint64_t seed);
+
+/* Copy N coordinates of bunch `bunch` in (where == MBT_HOST: host arrays,
+ * synchronous; MBT_DEVICE: device arrays, asynchronous on the bound stream). */
+int mbt_set_particles(mbt_ctx *ctx, int32_t bunch, const double *tau, const double *delta,
+                      int32_t where);
+
+/* Copy N coordinates of bunch `bunch` out; synchronises the bound stream. */
+int mbt_get_particles(mbt_ctx *ctx, int32_t bunch, double *tau, double *delta, int32_t where);
+
+/* Track nturns turns from the stored turn counter (so a checkpoint resumes).
+ *   out:    host array [nturns][M] of moments after each turn (may be NULL)
+ *   counts: host array [ceil(nturns/stride)][M][nbins] of bin counts of the
+ *           state after turns 0, stride, 2*stride, ... of this call (may be
+ *           NULL; needs a grid and stride >= 1)
+ * Each turn, for every bunch in bucket order: the kick (RF + harmonic cavity
+ * - U0 - short-range wake of the bin - long-range voltage), damping and
+ * quantum excitation with noise keyed by (seed, turn, stream ordinal,
+ * particle/2), then the drift (Sec. 2.2-2.4).  Blocks until done.
+ * MBT_ENUMERIC if a bunch moment became non-finite. */
+int mbt_track(mbt_ctx *ctx, int64_t nturns, mbt_moments *out, uint32_t *counts,
+              int32_t stride);
+
+/* Current line density: counts [M][nbins] of the present state on the grid
+ * (Sec. 2.3 binning).  Synchronises the bound stream. */
+int mbt_profile(mbt_ctx *ctx, uint32_t *counts);
+
+/* Binned wake potential [M][nbins] in V that the next turn would apply
+ * (Sec. 2.3): V[b][k] = (I_b T0 / N) sum_{m<=k} W[k-m] counts[b][m].
+ * Synchronises the bound stream. */
+int mbt_wake_potential(mbt_ctx *ctx, double *V);
+
+/* Wake table W[nbins] in V/C (W[0] = sum of W(0+)/2, W[k] = sum of W(k D)). */
+int mbt_wake_table(const mbt_ctx *ctx, double *W);
+
+/* Checkpoint state: turn counter, seed and the long-range phasors
+ * (phasors: [n_long_range][2] real, imaginary in V; may be NULL).  Together
+ * with the particle coordinates this resumes a run bit for bit. */
+int mbt_get_state(mbt_ctx *ctx, int64_t *turn, uint64_t *seed, double *phasors);
+int mbt_set_state(mbt_ctx *ctx, int64_t turn, uint64_t seed, const double *phasors);
+
+/* Kernel timing for measurement.  With every > 0, mbt_track records HIP
+ * events on the bound stream around the push launch and the between-turn
+ * launch of every `every`-th turn (at most 4096 of each per call) and adds
+ * their elapsed times to running totals; every = 0 switches it off and
+ * clears the totals.  mbt_get_timing returns the totals in milliseconds and
+ * the number of timed launches (any pointer may be NULL). */
+int mbt_set_timing(mbt_ctx *ctx, int32_t every);
+int mbt_get_timing(const mbt_ctx *ctx, double *push_ms, int64_t *push_launches,
+                   double *prep_ms, int64_t *prep_launches);
+
+/* Raw Philox-4x32-10 blocks on the device (the generator behind the noise,
+ * Salmon et al. SC'11): out[i][0..3] = philox(ctr[i][0..3], key), for
+ * n counters.  ctr and out are device arrays; asynchronous on hip_stream. */
+int mbt_philox4x32_10(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1,
+                      uint32_t *out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBT_H */

@@ -1,0 +1,101 @@
+"""ctypes declarations of the C ABI in include/mbt.h (argument marshalling only).
+
+Loads the in-tree libmbt.so.  There is no fallback: if the library is missing
+the import of the tracker fails with an error that says how to build it.
+"""
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbt.so")
+
+MBT_OK = 0
+MBT_EINVAL = -1
+MBT_ESTATE = -2
+MBT_ENOSPC = -3
+MBT_EDEVICE = -4
+MBT_ENUMERIC = -5
+MBT_ENOMEM = -6
+MBT_HOST = 0
+MBT_DEVICE = 1
+MBT_MAX_BINS = 4096
+MBT_MAX_SHORT_RANGE = 16
+MBT_MAX_LONG_RANGE = 4
+
+
+class Ring(C.Structure):
+    _fields_ = [("energy_eV", C.c_double), ("f_rf_Hz", C.c_double), ("v_rf_V", C.c_double),
+                ("alpha_c", C.c_double), ("u0_eV", C.c_double), ("tau_long_s", C.c_double),
+                ("sigma_delta", C.c_double), ("harmonic", C.c_int32)]
+
+
+class HC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("v_ratio", C.c_double), ("phase_n_rad", C.c_double)]
+
+
+class Resonator(C.Structure):
+    _fields_ = [("rs_ohm", C.c_double), ("q", C.c_double), ("fr_Hz", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nbins", C.c_int32), ("tau_min_s", C.c_double), ("tau_max_s", C.c_double)]
+
+
+class Moments(C.Structure):
+    _fields_ = [("mean_tau", C.c_double), ("mean_delta", C.c_double),
+                ("rms_tau", C.c_double), ("rms_delta", C.c_double)]
+
+
+_P = C.POINTER
+_ctx = C.c_void_p
+SIGNATURES = {
+    "mbt_strerror": (C.c_char_p, [C.c_int]),
+    "mbt_last_error": (C.c_char_p, [_ctx]),
+    "mbt_create": (C.c_int, [_P(Ring), _P(_ctx)]),
+    "mbt_destroy": (None, [_ctx]),
+    "mbt_hc_flat_fraction": (C.c_int, [_P(Ring), C.c_int32, C.c_double, _P(HC)]),
+    "mbt_set_harmonic_cavity": (C.c_int, [_ctx, _P(HC)]),
+    "mbt_set_fill": (C.c_int, [_ctx, C.c_int32, _P(C.c_int32), _P(C.c_double), _P(C.c_int32)]),
+    "mbt_set_short_range": (C.c_int, [_ctx, C.c_int32, _P(Resonator), _P(Grid)]),
+    "mbt_set_long_range": (C.c_int, [_ctx, C.c_int32, _P(Resonator)]),
+    "mbt_query_bytes": (C.c_int, [_ctx, C.c_int64, _P(C.c_size_t), _P(C.c_size_t)]),
+    "mbt_bind": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+                           C.c_void_p]),
+    "mbt_init_gaussian": (C.c_int, [_ctx, C.c_double, C.c_double, C.c_uint64]),
+    "mbt_set_particles": (C.c_int, [_ctx, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    "mbt_get_particles": (C.c_int, [_ctx, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    "mbt_track": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32]),
+    "mbt_profile": (C.c_int, [_ctx, C.c_void_p]),
+    "mbt_wake_potential": (C.c_int, [_ctx, C.c_void_p]),
+    "mbt_wake_table": (C.c_int, [_ctx, C.c_void_p]),
+    "mbt_get_state": (C.c_int, [_ctx, _P(C.c_int64), _P(C.c_uint64), C.c_void_p]),
+    "mbt_set_state": (C.c_int, [_ctx, C.c_int64, C.c_uint64, C.c_void_p]),
+    "mbt_set_timing": (C.c_int, [_ctx, C.c_int32]),
+    "mbt_get_timing": (C.c_int, [_ctx, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
+                                 _P(C.c_int64)]),
+    "mbt_philox4x32_10": (C.c_int, [C.c_int64, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p,
+                                    C.c_void_p]),
+}
+
+_lib = None
+
+
+class MissingLibraryError(ImportError):
+    pass
+
+
+def lib():
+    """The loaded libmbt.so with prototypes set; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MissingLibraryError(
+                f"{LIB_PATH} is not built; run `python paper_1809_00391_amd/build.py` "
+                "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib

@@ -1,0 +1,516 @@
+// mbt_kernels.hip -- HIP kernels of the longitudinal multi-bunch tracker for
+// CDNA4 (gfx950).
+//
+// One turn is two launches on the caller's stream:
+//   k_prep  (M [+1] workgroups): finishes the previous push's per-bunch sums
+//           (moments, Sec. 2.4), builds each bunch's binned wake potential
+//           from its line density (Sec. 2.3), and advances the long-range
+//           phasors bunch by bunch in bucket order (one extra workgroup).
+//   k_push  (tiles x M workgroups): the single-particle map of every particle
+//           (Sec. 2.2: Eq. 1 kick with RF, harmonic cavity and U0; Eq. 6
+//           short-range kick of the particle's bin; long-range kick; Eq. 5
+//           damping and quantum excitation; Eq. 2 drift), then -- on the new
+//           tau, which is exactly the tau the next turn bins -- the LDS
+//           histogram, the long-range deposit sums and the moment sums.
+// Particle coordinates are FP64 structure-of-arrays rows, one row per bunch;
+// each thread moves pairs of neighbouring particles with 16-byte loads and
+// stores, and one Philox block gives both particles of a pair their noise.
+// No floating-point atomics: all floating sums are fixed-order tile partials,
+// so a run is bit-reproducible; histograms use integer atomics.
+#include "mbt_internal.h"
+
+namespace mbt {
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_t &x2,
+                                             uint32_t &x3, uint32_t k0, uint32_t k1)
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+}
+
+__device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
+                                         uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        philox_round(x0, x1, x2, x3, k0, k1);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// 53 random bits to a double in (0, 1]: never 0, so the logarithm is finite.
+__device__ __forceinline__ double u01_open0(uint32_t lo, uint32_t hi)
+{
+    const uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return (double)(x >> 11) * 0x1.0p-53 + 0x1.0p-54;
+}
+
+// Box-Muller pair from one Philox block: z0 = r cos(theta), z1 = r sin(theta).
+__device__ __forceinline__ void normal_pair(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1, double &z0, double &z1)
+{
+    philox10(c0, c1, c2, c3, k0, k1);
+    const double u1 = u01_open0(c0, c1);
+    const double u2 = u01_open0(c2, c3);
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincos(6.283185307179586 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// ---------------------------------------------------------------------------
+// Map pieces.
+// ---------------------------------------------------------------------------
+
+// Bin of tau on the fixed grid; -1 outside [tau_min, tau_max) (and for NaN).
+__device__ __forceinline__ int bin_of(const MapConst &c, double t)
+{
+    const double x = (t - c.tau_min) * c.inv_delta;
+    return (x >= 0.0 && x < (double)c.nbins) ? (int)x : -1;
+}
+
+// Kick, damping + quantum excitation, drift of one particle (Sec. 2.2 Eqs. 1,
+// 5, 2 with the Eq. 6 short-range kick and the long-range kick).
+template <int NLR>
+__device__ __forceinline__ void kick_drift(const MapConst &c, const double *Vs,
+                                           const double (&seen)[NLR > 0 ? NLR : 1][2], double z,
+                                           double &t, double &d)
+{
+    double dE = c.v_rf * sin(c.phi_s - c.w_rf * t);
+    if (c.hc_on)
+        dE += c.hc_kv * sin(c.hc_nphi - c.hc_nw * t);
+    dE -= c.u0;
+    if (c.sr_on) {
+        const int k = bin_of(c, t);
+        if (k >= 0)
+            dE -= Vs[k];
+    }
+#pragma unroll
+    for (int r = 0; r < NLR; ++r) {
+        const double e = exp(-c.lr_alpha[r] * t);
+        double s, co;
+        sincos(c.lr_wbar[r] * t, &s, &co);
+        dE -= e * (seen[r][0] * co - seen[r][1] * s);
+    }
+    double dn = d + dE * c.inv_E0;
+    dn = dn * c.one_minus_D;
+    if (c.noise_on)
+        dn += c.noise * z;
+    d = dn;
+    t = t + c.drift * dn;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Per-particle epilogue on the new coordinates: histogram, sums of x and x^2
+// for the moments, long-range deposit sums.  The moment sums are plain (no
+// shift): bunch centroids stay within a few rms of the bucket centre, so the
+// variance keeps full precision, and the result depends only on the present
+// state, which makes a checkpointed run resume bit for bit.
+template <int NLR>
+__device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, double t, double d,
+                                         double *acc)
+{
+    if (c.sr_on) {
+        const int k = bin_of(c, t);
+        if (k >= 0)
+            atomicAdd(&hist_w[k], 1u);
+    }
+    acc[0] += t;
+    acc[1] += t * t;
+    acc[2] += d;
+    acc[3] += d * d;
+#pragma unroll
+    for (int r = 0; r < NLR; ++r) {
+        const double e = exp(c.lr_alpha[r] * t);
+        double s, co;
+        sincos(c.lr_wbar[r] * t, &s, &co);
+        acc[4 + 2 * r] += e * co;
+        acc[5 + 2 * r] -= e * s;
+    }
+}
+
+size_t push_lds_bytes(int nbins, int nsub)
+{
+    size_t v = (size_t)nbins * sizeof(double);
+    size_t h = (size_t)nsub * (size_t)nbins * sizeof(uint32_t);
+    h = (h + 7) & ~(size_t)7;
+    return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
+}
+
+int push_nsub(int nbins)
+{
+    if (nbins <= 0)
+        return 0;
+    if (nbins <= 1024)
+        return 4;
+    if (nbins <= 2048)
+        return 2;
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
+// k_push: grid (ntiles, M), 256 threads.  PUSH = false is the bin-only
+// prologue that produces the histogram, deposits and moments of the present
+// state without moving it.
+// ---------------------------------------------------------------------------
+template <int NLR, bool PUSH>
+__global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
+{
+    extern __shared__ double smem[];
+    const MapConst &c = a.c;
+    const int nb = c.nbins;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.y;
+    const int tile = blockIdx.x;
+
+    double *Vs = smem;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb);
+    double *red = smem + nb + ((a.nsub * nb + 1) >> 1);
+
+    for (int k = tid; k < a.nsub * nb; k += kPushThreads)
+        hist[k] = 0u;
+    if (PUSH && c.sr_on)
+        for (int k = tid; k < nb; k += kPushThreads)
+            Vs[k] = a.V[(size_t)b * nb + k];
+    __syncthreads();
+    uint32_t *hist_w = hist + (a.nsub > 0 ? (wave % a.nsub) * nb : 0);
+
+    double seen[NLR > 0 ? NLR : 1][2];
+#pragma unroll
+    for (int r = 0; r < NLR; ++r) {
+        seen[r][0] = a.seen[((size_t)r * a.M + b) * 2 + 0];
+        seen[r][1] = a.seen[((size_t)r * a.M + b) * 2 + 1];
+    }
+    const uint32_t stream = a.stream[b];
+
+    double *tau = a.tau + (size_t)b * a.ld;
+    double *del = a.delta + (size_t)b * a.ld;
+    constexpr int NP = 4 + 2 * NLR;
+    double acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+        acc[i] = 0.0;
+
+    const int64_t pair0 = (int64_t)tile * (kPushThreads * kPairsPerThread);
+    for (int it = 0; it < kPairsPerThread; ++it) {
+        const int64_t p = pair0 + (int64_t)it * kPushThreads + tid;
+        const int64_t j0 = 2 * p;
+        if (j0 >= a.N)
+            break;
+        const bool two = (j0 + 1) < a.N;
+        double t0, t1 = 0.0, d0, d1 = 0.0;
+        if (two) {
+            const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
+            const double2 dv = *reinterpret_cast<const double2 *>(del + j0);
+            t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
+        } else {
+            t0 = tau[j0];
+            d0 = del[j0];
+        }
+        if (PUSH) {
+            double z0 = 0.0, z1 = 0.0;
+            if (c.noise_on)
+                normal_pair((uint32_t)p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
+            kick_drift<NLR>(c, Vs, seen, z0, t0, d0);
+            if (two) {
+                kick_drift<NLR>(c, Vs, seen, z1, t1, d1);
+                *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
+                *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
+            } else {
+                tau[j0] = t0;
+                del[j0] = d0;
+            }
+        }
+        epilogue<NLR>(c, hist_w, t0, d0, acc);
+        if (two)
+            epilogue<NLR>(c, hist_w, t1, d1, acc);
+    }
+
+    // Fixed-order tile reduction: wave butterflies, then waves in order.
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const double v = wave_sum(acc[i]);
+        if (lane == 0)
+            red[wave * kPartStride + i] = v;
+    }
+    __syncthreads();
+    if (tid < NP) {
+        double s = red[tid];
+        for (int w = 1; w < kPushThreads / 64; ++w)
+            s += red[w * kPartStride + tid];
+        a.partials[((size_t)b * a.ntiles + tile) * kPartStride + tid] = s;
+    }
+    // Merge the LDS sub-histograms into the bunch's global histogram.
+    if (c.sr_on) {
+        for (int k = tid; k < nb; k += kPushThreads) {
+            uint32_t s = 0;
+            for (int q = 0; q < a.nsub; ++q)
+                s += hist[q * nb + k];
+            if (s)
+                atomicAdd(&a.counts_out[(size_t)b * nb + k], s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_prep: blocks 0..M-1 finish bunch b's moments and build its wake
+// potential; block M (when there are long-range resonators) advances the
+// phasors through the bunches in bucket order.
+// ---------------------------------------------------------------------------
+template <int NLR>
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
+{
+    extern __shared__ double psm[];
+    __shared__ double sred[kPrepThreads / 64][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    if ((int)blockIdx.x < a.M) {
+        const int b = blockIdx.x;
+        // Moments of the state the last push produced (Sec. 2.4).
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = tid; t < a.ntiles; t += kPrepThreads) {
+            const double *p = a.partials + ((size_t)b * a.ntiles + t) * kPartStride;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                s[i] += p[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double v = wave_sum(s[i]);
+            if (lane == 0)
+                sred[wave][i] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tot[4];
+            for (int i = 0; i < 4; ++i) {
+                tot[i] = sred[0][i];
+                for (int w = 1; w < kPrepThreads / 64; ++w)
+                    tot[i] += sred[w][i];
+            }
+            const double invN = 1.0 / (double)a.N;
+            const double mt = tot[0] * invN, md = tot[2] * invN;
+            const double vt = tot[1] * invN - mt * mt, vd = tot[3] * invN - md * md;
+            const double mean_t = mt, mean_d = md;
+            const double rms_t = sqrt(vt > 0.0 ? vt : 0.0), rms_d = sqrt(vd > 0.0 ? vd : 0.0);
+            if (a.mom_out) {
+                a.mom_out[4 * b + 0] = mean_t;
+                a.mom_out[4 * b + 1] = mean_d;
+                a.mom_out[4 * b + 2] = rms_t;
+                a.mom_out[4 * b + 3] = rms_d;
+            }
+            if (!isfinite(mean_t) || !isfinite(mean_d) || !isfinite(vt) || !isfinite(vd))
+                atomicOr(a.status, 1u);
+        }
+        if (!a.do_conv)
+            return;
+        // Wake potential of the binned line density (Sec. 2.3):
+        // V[k] = qpp * sum_{m<=k} W[k-m] c[m].
+        const int nb = a.nbins;
+        double *sW = psm;
+        double *sc = psm + nb;
+        int lo = nb;  // first occupied bin (Sec. 2.3): nothing below it
+        for (int k = tid; k < nb; k += kPrepThreads) {
+            sW[k] = a.W[k];
+            const uint32_t cnt = a.counts_in[(size_t)b * nb + k];
+            sc[k] = (double)cnt;
+            if (cnt && k < lo)
+                lo = k;
+        }
+        // block-wide min of the first occupied bin
+        __shared__ int s_lo;
+        if (tid == 0)
+            s_lo = nb;
+        __syncthreads();
+        atomicMin(&s_lo, lo);
+        __syncthreads();
+        lo = s_lo;
+        const double q = a.qpp[b];
+        for (int k = tid; k < nb; k += kPrepThreads) {
+            double acc = 0.0;
+            for (int m = lo; m <= k; ++m)
+                acc += sW[k - m] * sc[m];
+            a.V[(size_t)b * nb + k] = q * acc;
+            a.counts_clear[(size_t)b * nb + k] = 0u;
+        }
+        return;
+    }
+
+    // Long-range phasor scan (block M).
+    if (!a.do_scan || NLR == 0)
+        return;
+    const int chunk = 512;
+    double *sS = psm;  // [NLR][chunk][2]
+    double vr = 0.0, vi = 0.0;
+    if (tid < NLR) {
+        vr = a.phasor[2 * tid];
+        vi = a.phasor[2 * tid + 1];
+    }
+    for (int b0 = 0; b0 < a.M; b0 += chunk) {
+        const int nc = min(chunk, a.M - b0);
+        __syncthreads();
+        for (int idx = tid; idx < NLR * nc; idx += kPrepThreads) {
+            const int r = idx / nc, bb = idx - r * nc;
+            double sr = 0.0, si = 0.0;
+            const double *p = a.partials + (size_t)(b0 + bb) * a.ntiles * kPartStride + 4 + 2 * r;
+            for (int t = 0; t < a.ntiles; ++t) {
+                sr += p[(size_t)t * kPartStride];
+                si += p[(size_t)t * kPartStride + 1];
+            }
+            sS[(r * chunk + bb) * 2] = sr;
+            sS[(r * chunk + bb) * 2 + 1] = si;
+        }
+        __syncthreads();
+        if (tid < NLR) {
+            const int r = tid;
+            for (int bb = 0; bb < nc; ++bb) {
+                const size_t ix = ((size_t)r * a.M + b0 + bb) * 2;
+                // rotate across the gap from the previous filled bucket
+                const double gr = a.gap[ix], gi = a.gap[ix + 1];
+                const double nr = vr * gr - vi * gi;
+                const double ni = vr * gi + vi * gr;
+                vr = nr;
+                vi = ni;
+                a.seen[ix] = vr;
+                a.seen[ix + 1] = vi;
+                // deposit of this bunch: qpp * c_r * sum_j exp((alpha - i wbar) tau_j)
+                const double qr = a.qc[ix], qi = a.qc[ix + 1];
+                const double Sr = sS[(r * chunk + bb) * 2], Si = sS[(r * chunk + bb) * 2 + 1];
+                vr = vr + (qr * Sr - qi * Si);
+                vi = vi + (qr * Si + qi * Sr);
+            }
+        }
+    }
+    if (tid < NLR) {
+        a.phasor[2 * tid] = vr;
+        a.phasor[2 * tid + 1] = vi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial distribution and raw Philox.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init_gauss(double *tau, double *delta, int64_t ld,
+                                                    int64_t N, const uint32_t *stream,
+                                                    double sig_t, double sig_d, uint32_t k0,
+                                                    uint32_t k1)
+{
+    const int b = blockIdx.y;
+    const uint32_t sb = stream[b];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double z0, z1;
+        normal_pair((uint32_t)j, sb, 0u, 1u, k0, k1, z0, z1);
+        tau[(size_t)b * ld + j] = sig_t * z0;
+        delta[(size_t)b * ld + j] = sig_d * z1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_philox(int64_t n, const uint32_t *ctr, uint32_t k0,
+                                                uint32_t k1, uint32_t *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t x0 = ctr[4 * i], x1 = ctr[4 * i + 1], x2 = ctr[4 * i + 2], x3 = ctr[4 * i + 3];
+        philox10(x0, x1, x2, x3, k0, k1);
+        out[4 * i] = x0;
+        out[4 * i + 1] = x1;
+        out[4 * i + 2] = x2;
+        out[4 * i + 3] = x3;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <int NLR>
+static hipError_t push_n(const PushArgs &a, bool push, hipStream_t s)
+{
+    const dim3 grid(a.ntiles, a.M);
+    const size_t lds = push_lds_bytes(a.c.nbins, a.nsub);
+    if (push)
+        hipLaunchKernelGGL((k_push<NLR, true>), grid, dim3(kPushThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_push<NLR, false>), grid, dim3(kPushThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_push(const PushArgs &a, int nlr, bool push, hipStream_t s)
+{
+    if (a.ntiles < 1 || a.M < 1 || a.ntiles > 2147483647 || a.M > 65535)
+        return hipErrorInvalidValue;
+    switch (nlr) {
+    case 0: return push_n<0>(a, push, s);
+    case 1: return push_n<1>(a, push, s);
+    case 2: return push_n<2>(a, push, s);
+    case 3: return push_n<3>(a, push, s);
+    case 4: return push_n<4>(a, push, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
+{
+    const int blocks = a.M + ((a.do_scan && a.nlr > 0) ? 1 : 0);
+    size_t lds = (size_t)2 * a.nbins * sizeof(double);
+    const size_t scan_lds = (size_t)a.nlr * 512 * 2 * sizeof(double);
+    if (scan_lds > lds)
+        lds = scan_lds;
+    if (lds == 0)
+        lds = 16;
+    switch (a.nlr) {
+    case 0: hipLaunchKernelGGL((k_prep<0>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((k_prep<1>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_prep<2>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_prep<3>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_prep<4>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_gauss(double *tau, double *delta, int64_t ld, int64_t N, int M,
+                             const uint32_t *stream, double sig_tau, double sig_delta,
+                             uint32_t key0, uint32_t key1, hipStream_t s)
+{
+    int64_t bx = (N + 255) / 256;
+    if (bx > 4096)
+        bx = 4096;
+    hipLaunchKernelGGL(k_init_gauss, dim3((unsigned)bx, M), dim3(256), 0, s, tau, delta, ld, N,
+                       stream, sig_tau, sig_delta, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1,
+                         uint32_t *out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t bx = (n + 255) / 256;
+    if (bx > 8192)
+        bx = 8192;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)bx), dim3(256), 0, s, n, ctr, key0, key1, out);
+    return hipGetLastError();
+}
+
+}  // namespace mbt

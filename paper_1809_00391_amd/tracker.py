@@ -1,0 +1,218 @@
+"""Python binding of the tracker's C ABI (include/mbt.h).
+
+Argument marshalling only: every step of the turn runs in the HIP kernels of
+libmbt.so.  PyTorch provides the device memory (uint8 tensors handed over as
+raw pointers) and the stream.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import HC, Grid, Moments, Resonator, Ring
+
+__all__ = ["MbtError", "Tracker", "hc_flat_fraction", "philox4x32_10", "strerror"]
+
+
+class MbtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mbt error {code} ({strerror(code)}): {msg}")
+        self.code = code
+
+
+def strerror(code):
+    return _abi.lib().mbt_strerror(code).decode()
+
+
+def _ring(r):
+    return Ring(float(r["energy_eV"]), float(r["f_rf_Hz"]), float(r["v_rf_V"]),
+                float(r["alpha_c"]), float(r["u0_eV"]), float(r["tau_long_s"]),
+                float(r["sigma_delta"]), int(r["harmonic"]))
+
+
+def _resonators(res):
+    res = list(res)
+    return (Resonator * max(1, len(res)))(*[Resonator(*map(float, r)) for r in res]), len(res)
+
+
+def hc_flat_fraction(ring, n, frac):
+    """mbt_hc_flat_fraction: harmonic cavity at frac of the flat-potential voltage."""
+    out = HC()
+    rc = _abi.lib().mbt_hc_flat_fraction(C.byref(_ring(ring)), int(n), float(frac), C.byref(out))
+    if rc:
+        raise MbtError(rc, "no flat-potential solution")
+    return {"n": out.n, "v_ratio": out.v_ratio, "phase_n_rad": out.phase_n_rad}
+
+
+def philox4x32_10(ctr, key0, key1, stream=None):
+    """mbt_philox4x32_10 on a uint32 CUDA tensor ctr of shape [n, 4]."""
+    assert ctr.is_cuda and ctr.dtype == torch.int32 or ctr.dtype == torch.uint32
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _abi.lib().mbt_philox4x32_10(ctr.shape[0], C.c_void_p(ctr.data_ptr()), key0 & 0xFFFFFFFF,
+                                      key1 & 0xFFFFFFFF, C.c_void_p(out.data_ptr()),
+                                      C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MbtError(rc, "philox")
+    return out
+
+
+class Tracker:
+    """One tracking job: a context of the C ABI plus its device buffers."""
+
+    def __init__(self, ring):
+        self._L = _abi.lib()
+        self._h = C.c_void_p()
+        rc = self._L.mbt_create(C.byref(_ring(ring)), C.byref(self._h))
+        if rc:
+            raise MbtError(rc, "mbt_create: invalid ring parameters")
+        self.M = 0
+        self.N = 0
+        self.nbins = 0
+        self.n_lr = 0
+        self.state = None
+        self.work = None
+        self.stream = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.mbt_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise MbtError(rc, self._L.mbt_last_error(self._h).decode())
+
+    # ---- configuration ---------------------------------------------------
+    def set_harmonic_cavity(self, hc):
+        if hc is None:
+            self._check(self._L.mbt_set_harmonic_cavity(self._h, None))
+        else:
+            h = HC(int(hc["n"]), float(hc["v_ratio"]), float(hc["phase_n_rad"]))
+            self._check(self._L.mbt_set_harmonic_cavity(self._h, C.byref(h)))
+
+    def set_fill(self, buckets, currents_A, streams=None):
+        b = np.ascontiguousarray(buckets, dtype=np.int32)
+        c = np.ascontiguousarray(currents_A, dtype=np.float64)
+        s = None if streams is None else np.ascontiguousarray(streams, dtype=np.int32)
+        self._check(self._L.mbt_set_fill(
+            self._h, b.size, b.ctypes.data_as(C.POINTER(C.c_int32)),
+            c.ctypes.data_as(C.POINTER(C.c_double)),
+            None if s is None else s.ctypes.data_as(C.POINTER(C.c_int32))))
+        self.M = int(b.size)
+
+    def set_short_range(self, resonators, grid):
+        if grid is None:
+            self._check(self._L.mbt_set_short_range(self._h, 0, None, None))
+            self.nbins = 0
+            return
+        arr, n = _resonators(resonators)
+        g = Grid(int(grid[0]), float(grid[1]), float(grid[2]))
+        self._check(self._L.mbt_set_short_range(self._h, n, arr, C.byref(g)))
+        self.nbins = g.nbins
+
+    def set_long_range(self, resonators):
+        arr, n = _resonators(resonators)
+        self._check(self._L.mbt_set_long_range(self._h, n, arr))
+        self.n_lr = n
+
+    def query_bytes(self, N):
+        sb, wb = C.c_size_t(), C.c_size_t()
+        self._check(self._L.mbt_query_bytes(self._h, int(N), C.byref(sb), C.byref(wb)))
+        return sb.value, wb.value
+
+    def bind(self, N, device="cuda", stream=None):
+        """Allocate state and workspace as torch tensors and bind them."""
+        sb, wb = self.query_bytes(N)
+        self.state = torch.empty(sb + 256, dtype=torch.uint8, device=device)
+        self.work = torch.empty(wb + 256, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.state.device)
+        sp = (self.state.data_ptr() + 255) & ~255
+        wp = (self.work.data_ptr() + 255) & ~255
+        self._check(self._L.mbt_bind(self._h, int(N), C.c_void_p(sp), sb, C.c_void_p(wp), wb,
+                                     C.c_void_p(self.stream.cuda_stream)))
+        self.N = int(N)
+
+    # ---- particles and state -------------------------------------------
+    def init_gaussian(self, sigma_tau_s, sigma_delta, seed):
+        self._check(self._L.mbt_init_gaussian(self._h, float(sigma_tau_s), float(sigma_delta),
+                                              int(seed)))
+
+    def set_particles(self, bunch, tau, delta):
+        if isinstance(tau, torch.Tensor) and tau.is_cuda:
+            t = tau.to(torch.float64).contiguous()
+            d = delta.to(torch.float64).contiguous()
+            assert t.numel() == self.N and d.numel() == self.N
+            self._check(self._L.mbt_set_particles(self._h, int(bunch), C.c_void_p(t.data_ptr()),
+                                                  C.c_void_p(d.data_ptr()), _abi.MBT_DEVICE))
+            self.stream.synchronize()
+            return
+        t = np.ascontiguousarray(tau, dtype=np.float64)
+        d = np.ascontiguousarray(delta, dtype=np.float64)
+        assert t.size == self.N and d.size == self.N
+        self._check(self._L.mbt_set_particles(self._h, int(bunch), C.c_void_p(t.ctypes.data),
+                                              C.c_void_p(d.ctypes.data), _abi.MBT_HOST))
+
+    def get_particles(self, bunch):
+        t = np.empty(self.N)
+        d = np.empty(self.N)
+        self._check(self._L.mbt_get_particles(self._h, int(bunch), C.c_void_p(t.ctypes.data),
+                                              C.c_void_p(d.ctypes.data), _abi.MBT_HOST))
+        return t, d
+
+    def get_state(self):
+        turn, seed = C.c_int64(), C.c_uint64()
+        ph = np.zeros(2 * max(1, self.n_lr))
+        self._check(self._L.mbt_get_state(self._h, C.byref(turn), C.byref(seed),
+                                          C.c_void_p(ph.ctypes.data)))
+        return turn.value, seed.value, ph[:2 * self.n_lr].copy()
+
+    def set_state(self, turn, seed, phasors=None):
+        ph = None if phasors is None or len(phasors) == 0 else np.ascontiguousarray(phasors, np.float64)
+        self._check(self._L.mbt_set_state(self._h, int(turn), int(seed),
+                                          None if ph is None else C.c_void_p(ph.ctypes.data)))
+
+    # ---- tracking and observables ---------------------------------------
+    def track(self, nturns, profiles_stride=0, moments=True):
+        """Track nturns; returns moments [nturns][M][4] (and profiles)."""
+        mom = np.zeros((nturns, self.M, 4)) if moments else None
+        counts = None
+        if profiles_stride:
+            rows = -(-nturns // profiles_stride)
+            counts = np.zeros((rows, self.M, self.nbins), dtype=np.uint32)
+        self._check(self._L.mbt_track(
+            self._h, int(nturns), None if mom is None else C.c_void_p(mom.ctypes.data),
+            None if counts is None else C.c_void_p(counts.ctypes.data), int(profiles_stride)))
+        return (mom, counts) if profiles_stride else mom
+
+    def profile(self):
+        counts = np.zeros((self.M, self.nbins), dtype=np.uint32)
+        self._check(self._L.mbt_profile(self._h, C.c_void_p(counts.ctypes.data)))
+        return counts
+
+    def wake_potential(self):
+        V = np.zeros((self.M, self.nbins))
+        self._check(self._L.mbt_wake_potential(self._h, C.c_void_p(V.ctypes.data)))
+        return V
+
+    def set_timing(self, every):
+        self._check(self._L.mbt_set_timing(self._h, int(every)))
+
+    def get_timing(self):
+        """(push ms total, push launches timed, prep ms total, prep launches)."""
+        a, b, c, d = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
+        self._check(self._L.mbt_get_timing(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return a.value, b.value, c.value, d.value
+
+    def wake_table(self):
+        W = np.zeros(self.nbins)
+        self._check(self._L.mbt_wake_table(self._h, C.c_void_p(W.ctypes.data)))
+        return W

@@ -1,0 +1,135 @@
+"""The C-ABI library loads here (no GPU), exports every symbol include/mbt.h
+declares, and rejects bad arguments and bad call order on the host before
+any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1809_00391_amd import _abi
+from paper_1809_00391_amd import tracker as tr
+from paper_1809_00391_amd import workloads as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mbt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(mbt_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["mbt_create", "mbt_destroy", "mbt_set_fill", "mbt_set_short_range",
+                 "mbt_set_long_range", "mbt_set_harmonic_cavity", "mbt_hc_flat_fraction",
+                 "mbt_query_bytes", "mbt_bind", "mbt_init_gaussian", "mbt_set_particles",
+                 "mbt_get_particles", "mbt_track", "mbt_get_state", "mbt_set_state",
+                 "mbt_strerror", "mbt_last_error", "mbt_profile", "mbt_wake_potential",
+                 "mbt_wake_table", "mbt_philox4x32_10"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _abi.SIGNATURES, f"{n} has no Python prototype"
+
+
+def _ctx(ring=wl.RING_R480):
+    L = _abi.lib()
+    h = C.c_void_p()
+    rc = L.mbt_create(C.byref(tr._ring(ring)), C.byref(h))
+    return L, h, rc
+
+
+def test_create_validation():
+    bad = [dict(wl.RING_R480, energy_eV=-1.0), dict(wl.RING_R480, v_rf_V=0.4e6),
+           dict(wl.RING_R480, alpha_c=0.0), dict(wl.RING_R480, harmonic=0),
+           dict(wl.RING_R480, tau_long_s=0.0), dict(wl.RING_R480, sigma_delta=-1.0),
+           dict(wl.RING_R480, f_rf_Hz=float("nan"))]
+    for r in bad:
+        L, h, rc = _ctx(r)
+        assert rc == _abi.MBT_EINVAL and not h.value
+    L, h, rc = _ctx()
+    assert rc == 0 and h.value
+    L.mbt_destroy(h)
+    assert L.mbt_create(None, C.byref(C.c_void_p())) == _abi.MBT_EINVAL
+    L.mbt_destroy(None)  # allowed
+
+
+def test_call_order_and_argument_errors():
+    L, h, rc = _ctx()
+    sb, wb = C.c_size_t(), C.c_size_t()
+    assert L.mbt_query_bytes(h, 100, C.byref(sb), C.byref(wb)) == _abi.MBT_ESTATE
+    assert L.mbt_track(h, 10, None, None, 0) == _abi.MBT_ESTATE
+    assert L.mbt_init_gaussian(h, 1e-11, 1e-3, 1) == _abi.MBT_ESTATE
+    b = (C.c_int32 * 2)(0, 0)
+    cur = (C.c_double * 2)(1e-3, 1e-3)
+    assert L.mbt_set_fill(h, 2, b, cur, None) == _abi.MBT_EINVAL  # not increasing
+    b2 = (C.c_int32 * 2)(0, 480)
+    assert L.mbt_set_fill(h, 2, b2, cur, None) == _abi.MBT_EINVAL  # out of [0, h)
+    b3 = (C.c_int32 * 2)(0, 5)
+    neg = (C.c_double * 2)(1e-3, -1e-3)
+    assert L.mbt_set_fill(h, 2, b3, neg, None) == _abi.MBT_EINVAL
+    assert L.mbt_set_fill(h, 2, b3, cur, None) == 0
+    g = _abi.Grid(0, -1e-11, 1e-11)
+    res = (_abi.Resonator * 1)(_abi.Resonator(1e4, 1.0, 2e10))
+    assert L.mbt_set_short_range(h, 1, res, C.byref(g)) == _abi.MBT_EINVAL
+    g = _abi.Grid(64, 1e-11, -1e-11)
+    assert L.mbt_set_short_range(h, 1, res, C.byref(g)) == _abi.MBT_EINVAL
+    bad_q = (_abi.Resonator * 1)(_abi.Resonator(1e4, 0.5, 2e10))
+    g = _abi.Grid(64, -1e-11, 1e-11)
+    assert L.mbt_set_short_range(h, 1, bad_q, C.byref(g)) == _abi.MBT_EINVAL
+    assert L.mbt_set_short_range(h, 1, res, C.byref(g)) == 0
+    lr5 = (_abi.Resonator * 5)(*[_abi.Resonator(1e6, 2e4, 1.52e9)] * 5)
+    assert L.mbt_set_long_range(h, 5, lr5) == _abi.MBT_EINVAL  # > MBT_MAX_LONG_RANGE
+    assert L.mbt_set_long_range(h, 1, lr5) == 0
+    assert L.mbt_query_bytes(h, 0, C.byref(sb), C.byref(wb)) == _abi.MBT_EINVAL
+    assert L.mbt_query_bytes(h, 1000, C.byref(sb), C.byref(wb)) == 0
+    assert sb.value >= 2 * 2 * 1000 * 8 and wb.value > 0
+    # bind: null / misaligned pointers and undersized buffers fail before any device work
+    assert L.mbt_bind(h, 1000, None, sb.value, None, wb.value, None) == _abi.MBT_EINVAL
+    fake = C.c_void_p(1 << 20)
+    assert L.mbt_bind(h, 1000, C.c_void_p((1 << 20) + 8), sb.value, fake, wb.value,
+                      None) == _abi.MBT_EINVAL
+    assert L.mbt_bind(h, 1000, fake, sb.value - 8, fake, wb.value, None) == _abi.MBT_ENOSPC
+    assert b"need" in L.mbt_last_error(h)
+    assert L.mbt_philox4x32_10(-1, None, 0, 0, None, None) == _abi.MBT_EINVAL
+    L.mbt_destroy(h)
+
+
+def test_hc_flat_fraction_agrees_with_oracle():
+    from oracle import ref
+    for frac in (0.5, 0.9, 1.0):
+        for ring in (wl.RING_R480, dict(wl.RING_R480, alpha_c=-6e-4)):
+            a = tr.hc_flat_fraction(ring, 3, frac)
+            b = ref.hc_flat_fraction(ring, 3, frac)
+            assert a["v_ratio"] == pytest.approx(b["v_ratio"], rel=1e-15)
+            assert a["phase_n_rad"] == pytest.approx(b["phase_n_rad"], rel=1e-15)
+    with pytest.raises(tr.MbtError):
+        tr.hc_flat_fraction(dict(wl.RING_R480, u0_eV=1.4e6), 3, 1.0)
+
+
+def test_no_synchronous_phase_is_rejected():
+    t = tr.Tracker(wl.RING_R480)
+    with pytest.raises(tr.MbtError):
+        t.set_harmonic_cavity({"n": 3, "v_ratio": 10.0, "phase_n_rad": -1.5})
+    t.set_harmonic_cavity(tr.hc_flat_fraction(wl.RING_R480, 3, 0.9))
+
+
+def test_strerror():
+    for code in (0, -1, -2, -3, -4, -5, -6, 7):
+        assert isinstance(tr.strerror(code), str)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", "/nonexistent/libmbt.so")
+    with pytest.raises(_abi.MissingLibraryError):
+        _abi.lib()
