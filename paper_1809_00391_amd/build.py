@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmbt.so")
 SOURCES = [os.path.join(CSRC, "mbt_kernels.hip"), os.path.join(CSRC, "mbt_host.cpp")]
-HEADERS = [os.path.join(CSRC, "mbt_internal.h"), os.path.join(INCLUDE, "mbt.h")]
+HEADERS = [os.path.join(CSRC, "mbt_internal.h"), os.path.join(CSRC, "mbt_fastmath.h"),
+           os.path.join(INCLUDE, "mbt.h")]
 ARCH = os.environ.get("MBT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

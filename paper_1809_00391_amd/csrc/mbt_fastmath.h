@@ -1,0 +1,159 @@
+// mbt_fastmath.h -- FP64 sine, cosine and exponential used per particle by
+// the tracker kernels (host-callable too, so their accuracy is tested on the
+// CPU against extended-precision references).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace mbt {
+
+// ---------------------------------------------------------------------------
+// FP64 sine/cosine/exponential for the per-particle map.
+//
+// sincos_poly: sin and cos of |r| <= pi/4 from their Taylor series (the
+// coefficient of r^n is +-1/n!), truncated where the first dropped term is
+// below 1e-16 of the result, evaluated in Horner form in r^2 with FMAs.
+// sincos_cw: argument reduction by pi/2 after Cody and Waite (1980): with
+// k = rint(2x/pi), r = x - k*P1 - k*P2 where P1 is the double nearest pi/2
+// and P2 = pi/2 - P1, each step one FMA, then a quadrant swap.  Arguments
+// beyond 1e5 (never reached by particles near a bucket) use the library.
+// ---------------------------------------------------------------------------
+constexpr double kPio2Hi = 1.5707963267948966;     // double nearest pi/2
+constexpr double kPio2Lo = 6.123233995736766e-17;  // pi/2 - kPio2Hi
+constexpr double kTwoOverPi = 0.6366197723675814;
+
+__host__ __device__ __forceinline__ void sincos_poly(double r, double &s, double &c)
+{
+    const double z = r * r;
+    double ps = -1.0 / 1307674368000.0;           // -1/15!
+    ps = fma(ps, z, 1.0 / 6227020800.0);          //  1/13!
+    ps = fma(ps, z, -1.0 / 39916800.0);           // -1/11!
+    ps = fma(ps, z, 1.0 / 362880.0);              //  1/9!
+    ps = fma(ps, z, -1.0 / 5040.0);               // -1/7!
+    ps = fma(ps, z, 1.0 / 120.0);                 //  1/5!
+    ps = fma(ps, z, -1.0 / 6.0);                  // -1/3!
+    s = fma(r * z, ps, r);
+    double pc = 1.0 / 20922789888000.0;           //  1/16!
+    pc = fma(pc, z, -1.0 / 87178291200.0);        // -1/14!
+    pc = fma(pc, z, 1.0 / 479001600.0);           //  1/12!
+    pc = fma(pc, z, -1.0 / 3628800.0);            // -1/10!
+    pc = fma(pc, z, 1.0 / 40320.0);               //  1/8!
+    pc = fma(pc, z, -1.0 / 720.0);                // -1/6!
+    pc = fma(pc, z, 1.0 / 24.0);                  //  1/4!
+    pc = fma(pc, z, -0.5);                        // -1/2!
+    c = fma(z, pc, 1.0);
+}
+
+// x = q*pi/2 + r: rotate (sin r, cos r) into quadrant q.
+__host__ __device__ __forceinline__ void quadrant(int q, double sr, double cr, double &s, double &c)
+{
+    const double s0 = (q & 1) ? cr : sr;
+    const double c0 = (q & 1) ? sr : cr;
+    s = (q & 2) ? -s0 : s0;
+    c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// Library sine and cosine for the rare huge argument, kept out of line so
+// the per-particle loop stays small.
+__host__ __device__ __noinline__ void sincos_libm(double x, double &s, double &c)
+{
+    s = sin(x);
+    c = cos(x);
+}
+
+__host__ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
+{
+    if (!(fabs(x) < 1e5)) {
+        sincos_libm(x, s, c);
+        return;
+    }
+    const double k = rint(x * kTwoOverPi);
+    double r = fma(-k, kPio2Hi, x);
+    r = fma(-k, kPio2Lo, r);
+    double sr, cr;
+    sincos_poly(r, sr, cr);
+    quadrant((int)k, sr, cr, s, c);
+}
+
+// sin and cos of 2*pi*u for u in (0, 1]: 4u = k + f exactly (|f| <= 1/2),
+// angle f*pi/2 in [-pi/4, pi/4], quadrant k.
+__host__ __device__ __forceinline__ void sincos_2pi(double u, double &s, double &c)
+{
+    const double t = 4.0 * u;
+    const double k = rint(t);
+    double sr, cr;
+    sincos_poly((t - k) * kPio2Hi, sr, cr);
+    quadrant((int)k, sr, cr, s, c);
+}
+
+__host__ __device__ __noinline__ double exp_libm(double y) { return exp(y); }
+
+// exp(y): Taylor polynomial for |y| < 1e-3 (the long-range decay over one
+// bunch length: alpha*tau ~ 1e-5), otherwise the library.
+__host__ __device__ __forceinline__ double exp_small(double y)
+{
+    if (fabs(y) < 1e-3) {
+        double p = 1.0 / 120.0;
+        p = fma(p, y, 1.0 / 24.0);
+        p = fma(p, y, 1.0 / 6.0);
+        p = fma(p, y, 0.5);
+        p = fma(p, y, 1.0);
+        return fma(p, y, 1.0);
+    }
+    return exp_libm(y);
+}
+
+// (cos(n x), sin(n x)) from (cos x, sin x): the triple-angle identities for
+// n = 3 (sin 3x = sin x (3 - 4 sin^2 x), cos 3x = cos x (4 cos^2 x - 3)),
+// repeated complex products otherwise.
+__host__ __device__ __forceinline__ void multiple_angle(int n, double s1, double c1, double &sn, double &cn)
+{
+    if (n == 3) {
+        sn = s1 * fma(-4.0 * s1, s1, 3.0);
+        cn = c1 * fma(4.0 * c1, c1, -3.0);
+        return;
+    }
+    double s = s1, c = c1;
+    for (int i = 1; i < n; ++i) {
+        const double cs = fma(c, c1, -s * s1);
+        const double ss = fma(s, c1, c * s1);
+        c = cs;
+        s = ss;
+    }
+    sn = s;
+    cn = c;
+}
+
+// Natural logarithm of u in (0, 1] (the Box-Muller uniform).  u = m 2^e
+// with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1),
+// |s| < 0.172, from the series atanh(s) = s + s^3/3 + s^5/5 + ... truncated
+// after s^19/19 (the next term is below 2^-55 of the sum); e ln 2 is added
+// with ln 2 split into a 32-bit head and a tail so that e * head is exact.
+__host__ __device__ __forceinline__ double log_unit(double u)
+{
+    int e;
+    double m = frexp(u, &e);  // m in [1/2, 1)
+    if (m < 0.7071067811865476) {
+        m = m + m;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lm = fma(2.0 * s * z, p, 2.0 * s);
+    const double ln2_hi = 0.693147180369123816490;    // ln 2 to 32 bits
+    const double ln2_lo = 1.90821492927058770002e-10; // ln 2 - ln2_hi
+    const double de = (double)e;
+    return fma(de, ln2_hi, fma(de, ln2_lo, lm));
+}
+
+}  // namespace mbt

@@ -185,6 +185,8 @@ MapConst map_const(const mbt_ctx *c)
     m.v_rf = c->ring.v_rf_V;
     m.w_rf = c->w_rf;
     m.phi_s = c->phi_s;
+    m.sin_phis = std::sin(c->phi_s);
+    m.cos_phis = std::cos(c->phi_s);
     m.u0 = c->ring.u0_eV;
     m.one_minus_D = 1.0 - c->D;
     m.noise = c->noise;
@@ -194,6 +196,9 @@ MapConst map_const(const mbt_ctx *c)
         m.hc_kv = c->hc.v_ratio * c->ring.v_rf_V;
         m.hc_nphi = c->hc.phase_n_rad;
         m.hc_nw = (double)c->hc.n * c->w_rf;
+        m.hc_sin_nphi = std::sin(c->hc.phase_n_rad);
+        m.hc_cos_nphi = std::cos(c->hc.phase_n_rad);
+        m.hc_n = c->hc.n;
     }
     m.sr_on = c->sr_on ? 1 : 0;
     m.noise_on = c->noise > 0.0 ? 1 : 0;

@@ -21,6 +21,8 @@ struct MapConst {
     double v_rf;          // V_rf [V]
     double w_rf;          // 2 pi f_rf [rad/s]
     double phi_s;         // synchronous phase
+    double sin_phis;      // sin(phi_s)
+    double cos_phis;      // cos(phi_s)
     double u0;            // U0 [eV]
     double one_minus_D;   // 1 - D, D = 2 T0 / tau_L
     double noise;         // sigma_E sqrt(2 D)
@@ -28,6 +30,9 @@ struct MapConst {
     double hc_kv;         // k V_rf [V]
     double hc_nphi;       // n phi_h
     double hc_nw;         // n w_rf
+    double hc_sin_nphi;   // sin(n phi_h)
+    double hc_cos_nphi;   // cos(n phi_h)
+    int hc_n;             // harmonic of the cavity
     int hc_on;
     int sr_on;
     int noise_on;

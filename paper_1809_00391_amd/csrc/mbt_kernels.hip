@@ -2,10 +2,11 @@
 // CDNA4 (gfx950).
 //
 // One turn is two launches on the caller's stream:
-//   k_prep  (M [+1] workgroups): finishes the previous push's per-bunch sums
-//           (moments, Sec. 2.4), builds each bunch's binned wake potential
-//           from its line density (Sec. 2.3), and advances the long-range
-//           phasors bunch by bunch in bucket order (one extra workgroup).
+//   k_prep  (M x ceil(nbins/64) [+1] workgroups): finishes the previous
+//           push's per-bunch sums (moments, Sec. 2.4), builds each bunch's
+//           binned wake potential from its line density (Sec. 2.3), and
+//           advances the long-range phasors bunch by bunch in bucket order
+//           (one extra workgroup).
 //   k_push  (tiles x M workgroups): the single-particle map of every particle
 //           (Sec. 2.2: Eq. 1 kick with RF, harmonic cavity and U0; Eq. 6
 //           short-range kick of the particle's bin; long-range kick; Eq. 5
@@ -18,6 +19,7 @@
 // No floating-point atomics: all floating sums are fixed-order tile partials,
 // so a run is bit-reproducible; histograms use integer atomics.
 #include "mbt_internal.h"
+#include "mbt_fastmath.h"
 
 namespace mbt {
 
@@ -63,9 +65,9 @@ __device__ __forceinline__ void normal_pair(uint32_t c0, uint32_t c1, uint32_t c
     philox10(c0, c1, c2, c3, k0, k1);
     const double u1 = u01_open0(c0, c1);
     const double u2 = u01_open0(c2, c3);
-    const double r = sqrt(-2.0 * log(u1));
+    const double r = sqrt(-2.0 * log_unit(u1));
     double s, c;
-    sincos(6.283185307179586 * u2, &s, &c);
+    sincos_2pi(u2, s, c);
     z0 = r * c;
     z1 = r * s;
 }
@@ -88,9 +90,15 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double *Vs,
                                            const double (&seen)[NLR > 0 ? NLR : 1][2], double z,
                                            double &t, double &d)
 {
-    double dE = c.v_rf * sin(c.phi_s - c.w_rf * t);
-    if (c.hc_on)
-        dE += c.hc_kv * sin(c.hc_nphi - c.hc_nw * t);
+    // V_rf sin(phi_s - w tau) = V_rf [sin(phi_s) cos(w tau) - cos(phi_s) sin(w tau)]
+    double sx, cx;
+    sincos_cw(c.w_rf * t, sx, cx);
+    double dE = c.v_rf * (c.sin_phis * cx - c.cos_phis * sx);
+    if (c.hc_on) {
+        double sn, cn;
+        multiple_angle(c.hc_n, sx, cx, sn, cn);
+        dE += c.hc_kv * (c.hc_sin_nphi * cn - c.hc_cos_nphi * sn);
+    }
     dE -= c.u0;
     if (c.sr_on) {
         const int k = bin_of(c, t);
@@ -99,9 +107,9 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double *Vs,
     }
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
-        const double e = exp(-c.lr_alpha[r] * t);
+        const double e = exp_small(-c.lr_alpha[r] * t);
         double s, co;
-        sincos(c.lr_wbar[r] * t, &s, &co);
+        sincos_cw(c.lr_wbar[r] * t, s, co);
         dE -= e * (seen[r][0] * co - seen[r][1] * s);
     }
     double dn = d + dE * c.inv_E0;
@@ -140,9 +148,9 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
     acc[3] += d * d;
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
-        const double e = exp(c.lr_alpha[r] * t);
+        const double e = exp_small(c.lr_alpha[r] * t);
         double s, co;
-        sincos(c.lr_wbar[r] * t, &s, &co);
+        sincos_cw(c.lr_wbar[r] * t, s, co);
         acc[4 + 2 * r] += e * co;
         acc[5 + 2 * r] -= e * s;
     }
@@ -211,13 +219,15 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
     for (int i = 0; i < NP; ++i)
         acc[i] = 0.0;
 
-    const int64_t pair0 = (int64_t)tile * (kPushThreads * kPairsPerThread);
+    // Indices within the bunch fit 32 bits (N <= 2^32, so a pair index < 2^31).
+    const uint32_t pair0 = (uint32_t)tile * (kPushThreads * kPairsPerThread);
+    const uint32_t n_part = (uint32_t)(a.N - 1);  // last particle index
     for (int it = 0; it < kPairsPerThread; ++it) {
-        const int64_t p = pair0 + (int64_t)it * kPushThreads + tid;
-        const int64_t j0 = 2 * p;
-        if (j0 >= a.N)
+        const uint32_t p = pair0 + (uint32_t)(it * kPushThreads + tid);
+        const uint32_t j0 = 2u * p;
+        if (j0 > n_part)
             break;
-        const bool two = (j0 + 1) < a.N;
+        const bool two = j0 < n_part;
         double t0, t1 = 0.0, d0, d1 = 0.0;
         if (two) {
             const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
@@ -230,7 +240,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
         if (PUSH) {
             double z0 = 0.0, z1 = 0.0;
             if (c.noise_on)
-                normal_pair((uint32_t)p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
+                normal_pair(p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
             kick_drift<NLR>(c, Vs, seen, z0, t0, d0);
             if (two) {
                 kick_drift<NLR>(c, Vs, seen, z1, t1, d1);
@@ -273,92 +283,111 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// k_prep: blocks 0..M-1 finish bunch b's moments and build its wake
-// potential; block M (when there are long-range resonators) advances the
-// phasors through the bunches in bucket order.
+// k_prep: per bunch b, ceil(nbins/64) workgroups; the first of them also
+// finishes the bunch's moments.  Each workgroup builds 64 bins of the
+// bunch's wake potential, one wavefront per output bin with the lanes
+// splitting the sum over source bins.  One extra workgroup (when there are
+// long-range resonators) advances the phasors through the bunches in bucket
+// order.
 // ---------------------------------------------------------------------------
-template <int NLR>
-__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
+constexpr int kConvOut = 64;
+
+// Moments of bunch b from the tile sums of the last push (Sec. 2.4).
+__device__ void finish_moments(const PrepArgs &a, int b)
 {
-    extern __shared__ double psm[];
     __shared__ double sred[kPrepThreads / 64][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    if ((int)blockIdx.x < a.M) {
-        const int b = blockIdx.x;
-        // Moments of the state the last push produced (Sec. 2.4).
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int t = tid; t < a.ntiles; t += kPrepThreads) {
-            const double *p = a.partials + ((size_t)b * a.ntiles + t) * kPartStride;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = tid; t < a.ntiles; t += kPrepThreads) {
+        const double *p = a.partials + ((size_t)b * a.ntiles + t) * kPartStride;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                s[i] += p[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double v = wave_sum(s[i]);
-            if (lane == 0)
-                sred[wave][i] = v;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double tot[4];
-            for (int i = 0; i < 4; ++i) {
-                tot[i] = sred[0][i];
-                for (int w = 1; w < kPrepThreads / 64; ++w)
-                    tot[i] += sred[w][i];
-            }
-            const double invN = 1.0 / (double)a.N;
-            const double mt = tot[0] * invN, md = tot[2] * invN;
-            const double vt = tot[1] * invN - mt * mt, vd = tot[3] * invN - md * md;
-            const double mean_t = mt, mean_d = md;
-            const double rms_t = sqrt(vt > 0.0 ? vt : 0.0), rms_d = sqrt(vd > 0.0 ? vd : 0.0);
-            if (a.mom_out) {
-                a.mom_out[4 * b + 0] = mean_t;
-                a.mom_out[4 * b + 1] = mean_d;
-                a.mom_out[4 * b + 2] = rms_t;
-                a.mom_out[4 * b + 3] = rms_d;
-            }
-            if (!isfinite(mean_t) || !isfinite(mean_d) || !isfinite(vt) || !isfinite(vd))
-                atomicOr(a.status, 1u);
-        }
-        if (!a.do_conv)
-            return;
-        // Wake potential of the binned line density (Sec. 2.3):
-        // V[k] = qpp * sum_{m<=k} W[k-m] c[m].
-        const int nb = a.nbins;
-        double *sW = psm;
-        double *sc = psm + nb;
-        int lo = nb;  // first occupied bin (Sec. 2.3): nothing below it
-        for (int k = tid; k < nb; k += kPrepThreads) {
-            sW[k] = a.W[k];
-            const uint32_t cnt = a.counts_in[(size_t)b * nb + k];
-            sc[k] = (double)cnt;
-            if (cnt && k < lo)
-                lo = k;
-        }
-        // block-wide min of the first occupied bin
-        __shared__ int s_lo;
-        if (tid == 0)
-            s_lo = nb;
-        __syncthreads();
-        atomicMin(&s_lo, lo);
-        __syncthreads();
-        lo = s_lo;
-        const double q = a.qpp[b];
-        for (int k = tid; k < nb; k += kPrepThreads) {
-            double acc = 0.0;
-            for (int m = lo; m <= k; ++m)
-                acc += sW[k - m] * sc[m];
-            a.V[(size_t)b * nb + k] = q * acc;
-            a.counts_clear[(size_t)b * nb + k] = 0u;
-        }
-        return;
+        for (int i = 0; i < 4; ++i)
+            s[i] += p[i];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double v = wave_sum(s[i]);
+        if (lane == 0)
+            sred[wave][i] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double tot[4];
+        for (int i = 0; i < 4; ++i) {
+            tot[i] = sred[0][i];
+            for (int w = 1; w < kPrepThreads / 64; ++w)
+                tot[i] += sred[w][i];
+        }
+        const double invN = 1.0 / (double)a.N;
+        const double mt = tot[0] * invN, md = tot[2] * invN;
+        const double vt = tot[1] * invN - mt * mt, vd = tot[3] * invN - md * md;
+        const double rms_t = sqrt(vt > 0.0 ? vt : 0.0), rms_d = sqrt(vd > 0.0 ? vd : 0.0);
+        if (a.mom_out) {
+            a.mom_out[4 * b + 0] = mt;
+            a.mom_out[4 * b + 1] = md;
+            a.mom_out[4 * b + 2] = rms_t;
+            a.mom_out[4 * b + 3] = rms_d;
+        }
+        if (!isfinite(mt) || !isfinite(md) || !isfinite(vt) || !isfinite(vd))
+            atomicOr(a.status, 1u);
+    }
+}
 
-    // Long-range phasor scan (block M).
-    if (!a.do_scan || NLR == 0)
-        return;
+// Bins [k0, k1) of bunch b's wake potential (Sec. 2.3):
+// V[k] = qpp * sum_{m<=k} W[k-m] c[m].  Four threads per output bin, each
+// summing every fourth source bin with two accumulators; the four partial
+// sums are added in a fixed order.
+__device__ void conv_chunk(const PrepArgs &a, int b, int chunk, double *psm)
+{
+    __shared__ int s_lo;
+    __shared__ double part[4][kConvOut];
+    const int tid = threadIdx.x;
+    const int nb = a.nbins;
+    const int k0 = chunk * kConvOut, k1 = min(k0 + kConvOut, nb);
+    double *sW = psm;        // W[0 .. k1)
+    double *sc = psm + nb;   // c[0 .. k1)
+    if (tid == 0)
+        s_lo = k1;
+    __syncthreads();
+    int lo = k1;             // first occupied bin: nothing below it contributes
+    for (int k = tid; k < k1; k += kPrepThreads) {
+        sW[k] = a.W[k];
+        const uint32_t cnt = a.counts_in[(size_t)b * nb + k];
+        sc[k] = (double)cnt;
+        if (cnt && k < lo)
+            lo = k;
+    }
+    if (lo < k1)
+        atomicMin(&s_lo, lo);
+    __syncthreads();
+    lo = s_lo;
+    const int o = tid & (kConvOut - 1), q = tid / kConvOut;  // output, quarter
+    const int k = k0 + o;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (k < k1) {
+        int m = lo + q;
+        for (; m + 4 <= k; m += 8) {
+            acc0 += sW[k - m] * sc[m];
+            acc1 += sW[k - m - 4] * sc[m + 4];
+        }
+        if (m <= k)
+            acc0 += sW[k - m] * sc[m];
+    }
+    part[q][o] = acc0 + acc1;
+    __syncthreads();
+    if (tid < kConvOut && k < k1)
+        a.V[(size_t)b * nb + k] = a.qpp[b] * (((part[0][o] + part[1][o]) + part[2][o]) + part[3][o]);
+    for (int kk = k0 + tid; kk < k1; kk += kPrepThreads)
+        a.counts_clear[(size_t)b * nb + kk] = 0u;
+}
+
+// Long-range phasors advanced bunch by bunch in bucket order: rotate across
+// the gap from the previous filled bucket, record the voltage the bunch
+// sees, add the bunch's deposit qpp * c_r * sum_j exp((alpha - i wbar) tau_j).
+template <int NLR>
+__device__ void phasor_scan(const PrepArgs &a, double *psm)
+{
+    const int tid = threadIdx.x;
     const int chunk = 512;
     double *sS = psm;  // [NLR][chunk][2]
     double vr = 0.0, vi = 0.0;
@@ -385,7 +414,6 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
             const int r = tid;
             for (int bb = 0; bb < nc; ++bb) {
                 const size_t ix = ((size_t)r * a.M + b0 + bb) * 2;
-                // rotate across the gap from the previous filled bucket
                 const double gr = a.gap[ix], gi = a.gap[ix + 1];
                 const double nr = vr * gr - vi * gi;
                 const double ni = vr * gi + vi * gr;
@@ -393,7 +421,6 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
                 vi = ni;
                 a.seen[ix] = vr;
                 a.seen[ix + 1] = vi;
-                // deposit of this bunch: qpp * c_r * sum_j exp((alpha - i wbar) tau_j)
                 const double qr = a.qc[ix], qi = a.qc[ix + 1];
                 const double Sr = sS[(r * chunk + bb) * 2], Si = sS[(r * chunk + bb) * 2 + 1];
                 vr = vr + (qr * Sr - qi * Si);
@@ -405,6 +432,29 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
         a.phasor[2 * tid] = vr;
         a.phasor[2 * tid + 1] = vi;
     }
+}
+
+static __host__ __device__ inline int conv_chunks(const PrepArgs &a)
+{
+    return a.do_conv ? (a.nbins + kConvOut - 1) / kConvOut : 1;
+}
+
+template <int NLR>
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
+{
+    extern __shared__ double psm[];
+    const int nchunks = conv_chunks(a);
+    const int blk = blockIdx.x;
+    if (blk < a.M * nchunks) {
+        const int b = blk / nchunks, chunk = blk - b * nchunks;
+        if (chunk == 0)
+            finish_moments(a, b);
+        if (a.do_conv)
+            conv_chunk(a, b, chunk, psm);
+        return;
+    }
+    if (a.do_scan && NLR > 0)
+        phasor_scan<NLR>(a, psm);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,7 +521,7 @@ hipError_t launch_push(const PushArgs &a, int nlr, bool push, hipStream_t s)
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
 {
-    const int blocks = a.M + ((a.do_scan && a.nlr > 0) ? 1 : 0);
+    const int blocks = a.M * conv_chunks(a) + ((a.do_scan && a.nlr > 0) ? 1 : 0);
     size_t lds = (size_t)2 * a.nbins * sizeof(double);
     const size_t scan_lds = (size_t)a.nlr * 512 * 2 * sizeof(double);
     if (scan_lds > lds)
