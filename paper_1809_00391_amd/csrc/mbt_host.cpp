@@ -181,23 +181,20 @@ int solve_phi_s(mbt_ctx *c, bool hc_on, const mbt_hc &hc, double *phi)
 MapConst map_const(const mbt_ctx *c)
 {
     MapConst m{};
-    m.inv_E0 = 1.0 / c->ring.energy_eV;
-    m.v_rf = c->ring.v_rf_V;
+    const double E0 = c->ring.energy_eV;
+    m.inv_E0 = 1.0 / E0;
     m.w_rf = c->w_rf;
-    m.phi_s = c->phi_s;
-    m.sin_phis = std::sin(c->phi_s);
-    m.cos_phis = std::cos(c->phi_s);
-    m.u0 = c->ring.u0_eV;
+    m.rf_a = c->ring.v_rf_V * std::sin(c->phi_s) / E0;
+    m.rf_b = c->ring.v_rf_V * std::cos(c->phi_s) / E0;
+    m.u0_e = c->ring.u0_eV / E0;
     m.one_minus_D = 1.0 - c->D;
     m.noise = c->noise;
     m.drift = c->drift;
     m.hc_on = c->hc_on ? 1 : 0;
     if (c->hc_on) {
-        m.hc_kv = c->hc.v_ratio * c->ring.v_rf_V;
-        m.hc_nphi = c->hc.phase_n_rad;
-        m.hc_nw = (double)c->hc.n * c->w_rf;
-        m.hc_sin_nphi = std::sin(c->hc.phase_n_rad);
-        m.hc_cos_nphi = std::cos(c->hc.phase_n_rad);
+        const double kv = c->hc.v_ratio * c->ring.v_rf_V;
+        m.hc_a = kv * std::sin(c->hc.phase_n_rad) / E0;
+        m.hc_b = kv * std::cos(c->hc.phase_n_rad) / E0;
         m.hc_n = c->hc.n;
     }
     m.sr_on = c->sr_on ? 1 : 0;

@@ -18,20 +18,15 @@ constexpr int kRowAlign = 64;        // particle rows padded to 64 doubles (512 
 // Per-turn constants of the single-particle map and the binning grid.
 struct MapConst {
     double inv_E0;        // 1/E0 [1/eV]
-    double v_rf;          // V_rf [V]
     double w_rf;          // 2 pi f_rf [rad/s]
-    double phi_s;         // synchronous phase
-    double sin_phis;      // sin(phi_s)
-    double cos_phis;      // cos(phi_s)
-    double u0;            // U0 [eV]
+    double rf_a;          // V_rf sin(phi_s) / E0
+    double rf_b;          // V_rf cos(phi_s) / E0
+    double u0_e;          // U0 / E0
     double one_minus_D;   // 1 - D, D = 2 T0 / tau_L
     double noise;         // sigma_E sqrt(2 D)
     double drift;         // alpha_c T0 [s]
-    double hc_kv;         // k V_rf [V]
-    double hc_nphi;       // n phi_h
-    double hc_nw;         // n w_rf
-    double hc_sin_nphi;   // sin(n phi_h)
-    double hc_cos_nphi;   // cos(n phi_h)
+    double hc_a;          // k V_rf sin(n phi_h) / E0
+    double hc_b;          // k V_rf cos(n phi_h) / E0
     int hc_n;             // harmonic of the cavity
     int hc_on;
     int sr_on;

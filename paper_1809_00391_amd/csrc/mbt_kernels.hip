@@ -43,6 +43,11 @@ __device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_
 __device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
                                          uint32_t k0, uint32_t k1)
 {
+    // The key is uniform across the wavefront; marking it as redefined here
+    // keeps the compiler from hoisting all ten round keys out of the particle
+    // loop (twenty scalar registers), so each round adds its Weyl step with
+    // one scalar instruction instead.
+    __asm__ volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         philox_round(x0, x1, x2, x3, k0, k1);
@@ -83,41 +88,58 @@ __device__ __forceinline__ int bin_of(const MapConst &c, double t)
     return (x >= 0.0 && x < (double)c.nbins) ? (int)x : -1;
 }
 
+// sin and cos of the RF phase x = w_rf tau of a pair of particles.  Near the
+// synchronous particle (every lane of the wavefront within |x| <= pi/4) the
+// Taylor polynomials apply directly; otherwise reduce by pi/2 first.
+__device__ __forceinline__ void rf_phase(double x0, double x1, double &s0, double &c0, double &s1,
+                                         double &c1)
+{
+    constexpr double kPio4 = 0.7853981633974483;
+    if (__all(fabs(x0) <= kPio4 && fabs(x1) <= kPio4)) {
+        sincos_poly(x0, s0, c0);
+        sincos_poly(x1, s1, c1);
+    } else {
+        sincos_cw(x0, s0, c0);
+        sincos_cw(x1, s1, c1);
+    }
+}
+
 // Kick, damping + quantum excitation, drift of one particle (Sec. 2.2 Eqs. 1,
-// 5, 2 with the Eq. 6 short-range kick and the long-range kick).
+// 5, 2 with the Eq. 6 short-range kick and the long-range kick), all energy
+// terms in units of E0:
+//   RF:  V_rf sin(phi_s - w tau)/E0 = a cos(w tau) - b sin(w tau)
+//   HC:  k V_rf sin(n phi_h - n w tau)/E0 = a_h cos(n w tau) - b_h sin(n w tau)
+//   wake: the bin's V/E0 (staged in LDS already divided by E0)
+//   long range: Re[(V~/E0) exp((-alpha + i wbar) tau)]
 template <int NLR>
 __device__ __forceinline__ void kick_drift(const MapConst &c, const double *Vs,
-                                           const double (&seen)[NLR > 0 ? NLR : 1][2], double z,
-                                           double &t, double &d)
+                                           const double (&seen)[NLR > 0 ? NLR : 1][2], double sx,
+                                           double cx, double z, double &t, double &d)
 {
-    // V_rf sin(phi_s - w tau) = V_rf [sin(phi_s) cos(w tau) - cos(phi_s) sin(w tau)]
-    double sx, cx;
-    sincos_cw(c.w_rf * t, sx, cx);
-    double dE = c.v_rf * (c.sin_phis * cx - c.cos_phis * sx);
+    double k = fma(c.rf_a, cx, -c.rf_b * sx);
     if (c.hc_on) {
         double sn, cn;
         multiple_angle(c.hc_n, sx, cx, sn, cn);
-        dE += c.hc_kv * (c.hc_sin_nphi * cn - c.hc_cos_nphi * sn);
+        k += fma(c.hc_a, cn, -c.hc_b * sn);
     }
-    dE -= c.u0;
+    k -= c.u0_e;
     if (c.sr_on) {
-        const int k = bin_of(c, t);
-        if (k >= 0)
-            dE -= Vs[k];
+        const int kb = bin_of(c, t);
+        if (kb >= 0)
+            k -= Vs[kb];
     }
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
         const double e = exp_small(-c.lr_alpha[r] * t);
         double s, co;
         sincos_cw(c.lr_wbar[r] * t, s, co);
-        dE -= e * (seen[r][0] * co - seen[r][1] * s);
+        k -= e * fma(seen[r][0], co, -seen[r][1] * s);
     }
-    double dn = d + dE * c.inv_E0;
-    dn = dn * c.one_minus_D;
+    double dn = (d + k) * c.one_minus_D;
     if (c.noise_on)
-        dn += c.noise * z;
+        dn = fma(c.noise, z, dn);
     d = dn;
-    t = t + c.drift * dn;
+    t = fma(c.drift, dn, t);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -143,16 +165,16 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
             atomicAdd(&hist_w[k], 1u);
     }
     acc[0] += t;
-    acc[1] += t * t;
+    acc[1] = fma(t, t, acc[1]);
     acc[2] += d;
-    acc[3] += d * d;
+    acc[3] = fma(d, d, acc[3]);
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
         const double e = exp_small(c.lr_alpha[r] * t);
         double s, co;
         sincos_cw(c.lr_wbar[r] * t, s, co);
-        acc[4 + 2 * r] += e * co;
-        acc[5 + 2 * r] -= e * s;
+        acc[4 + 2 * r] = fma(e, co, acc[4 + 2 * r]);
+        acc[5 + 2 * r] = fma(-e, s, acc[5 + 2 * r]);
     }
 }
 
@@ -175,10 +197,50 @@ int push_nsub(int nbins)
     return 1;
 }
 
+// One pair of neighbouring particles j0, j0 + 1 (the second only if `two`).
+template <int NLR, bool PUSH>
+__device__ __forceinline__ void pair_step(const PushArgs &a, const double *Vs,
+                                          const double (&seen)[NLR > 0 ? NLR : 1][2],
+                                          uint32_t *hist_w, double *tau, double *del, uint32_t p,
+                                          uint32_t stream, bool two, double *acc)
+{
+    const MapConst &c = a.c;
+    const uint32_t j0 = 2u * p;
+    double t0, t1 = 0.0, d0, d1 = 0.0;
+    if (two) {
+        const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
+        const double2 dv = *reinterpret_cast<const double2 *>(del + j0);
+        t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
+    } else {
+        t0 = tau[j0];
+        d0 = del[j0];
+    }
+    if (PUSH) {
+        double z0 = 0.0, z1 = 0.0;
+        if (c.noise_on)
+            normal_pair(p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
+        double s0, c0, s1, c1;
+        rf_phase(c.w_rf * t0, c.w_rf * t1, s0, c0, s1, c1);
+        kick_drift<NLR>(c, Vs, seen, s0, c0, z0, t0, d0);
+        kick_drift<NLR>(c, Vs, seen, s1, c1, z1, t1, d1);
+        if (two) {
+            *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
+            *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
+        } else {
+            tau[j0] = t0;
+            del[j0] = d0;
+        }
+    }
+    epilogue<NLR>(c, hist_w, t0, d0, acc);
+    if (two)
+        epilogue<NLR>(c, hist_w, t1, d1, acc);
+}
+
 // ---------------------------------------------------------------------------
 // k_push: grid (ntiles, M), 256 threads.  PUSH = false is the bin-only
 // prologue that produces the histogram, deposits and moments of the present
-// state without moving it.
+// state without moving it.  All tiles but a bunch's last are full and run a
+// loop without bounds checks.
 // ---------------------------------------------------------------------------
 template <int NLR, bool PUSH>
 __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
@@ -199,15 +261,15 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
         hist[k] = 0u;
     if (PUSH && c.sr_on)
         for (int k = tid; k < nb; k += kPushThreads)
-            Vs[k] = a.V[(size_t)b * nb + k];
+            Vs[k] = a.V[(size_t)b * nb + k] * c.inv_E0;
     __syncthreads();
     uint32_t *hist_w = hist + (a.nsub > 0 ? (wave % a.nsub) * nb : 0);
 
     double seen[NLR > 0 ? NLR : 1][2];
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
-        seen[r][0] = a.seen[((size_t)r * a.M + b) * 2 + 0];
-        seen[r][1] = a.seen[((size_t)r * a.M + b) * 2 + 1];
+        seen[r][0] = a.seen[((size_t)r * a.M + b) * 2 + 0] * c.inv_E0;
+        seen[r][1] = a.seen[((size_t)r * a.M + b) * 2 + 1] * c.inv_E0;
     }
     const uint32_t stream = a.stream[b];
 
@@ -221,39 +283,20 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
 
     // Indices within the bunch fit 32 bits (N <= 2^32, so a pair index < 2^31).
     const uint32_t pair0 = (uint32_t)tile * (kPushThreads * kPairsPerThread);
-    const uint32_t n_part = (uint32_t)(a.N - 1);  // last particle index
-    for (int it = 0; it < kPairsPerThread; ++it) {
-        const uint32_t p = pair0 + (uint32_t)(it * kPushThreads + tid);
-        const uint32_t j0 = 2u * p;
-        if (j0 > n_part)
-            break;
-        const bool two = j0 < n_part;
-        double t0, t1 = 0.0, d0, d1 = 0.0;
-        if (two) {
-            const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
-            const double2 dv = *reinterpret_cast<const double2 *>(del + j0);
-            t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
-        } else {
-            t0 = tau[j0];
-            d0 = del[j0];
+    if ((int64_t)(pair0 + kPushThreads * kPairsPerThread) * 2 <= a.N) {
+#pragma unroll 1
+        for (int it = 0; it < kPairsPerThread; ++it)
+            pair_step<NLR, PUSH>(a, Vs, seen, hist_w, tau, del,
+                                 pair0 + (uint32_t)(it * kPushThreads + tid), stream, true, acc);
+    } else {
+        const uint32_t n_part = (uint32_t)(a.N - 1);  // last particle index
+#pragma unroll 1
+        for (int it = 0; it < kPairsPerThread; ++it) {
+            const uint32_t p = pair0 + (uint32_t)(it * kPushThreads + tid);
+            if (2u * p > n_part)
+                break;
+            pair_step<NLR, PUSH>(a, Vs, seen, hist_w, tau, del, p, stream, 2u * p < n_part, acc);
         }
-        if (PUSH) {
-            double z0 = 0.0, z1 = 0.0;
-            if (c.noise_on)
-                normal_pair(p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
-            kick_drift<NLR>(c, Vs, seen, z0, t0, d0);
-            if (two) {
-                kick_drift<NLR>(c, Vs, seen, z1, t1, d1);
-                *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
-                *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
-            } else {
-                tau[j0] = t0;
-                del[j0] = d0;
-            }
-        }
-        epilogue<NLR>(c, hist_w, t0, d0, acc);
-        if (two)
-            epilogue<NLR>(c, hist_w, t1, d1, acc);
     }
 
     // Fixed-order tile reduction: wave butterflies, then waves in order.
