@@ -5,8 +5,8 @@
 //   k_prep  (M x ceil(nbins/64) [+1] workgroups): finishes the previous
 //           push's per-bunch sums (moments, Sec. 2.4), builds each bunch's
 //           binned wake potential from its line density (Sec. 2.3), and
-//           advances the long-range phasors bunch by bunch in bucket order
-//           (one extra workgroup).
+//           advances the long-range phasors through the bunches in bucket
+//           order (one extra workgroup, as a scan of affine maps).
 //   k_push  (tiles x M workgroups): the single-particle map of every particle
 //           (Sec. 2.2: Eq. 1 kick with RF, harmonic cavity and U0; Eq. 6
 //           short-range kick of the particle's bin; long-range kick; Eq. 5
@@ -155,6 +155,9 @@ __device__ __forceinline__ double wave_sum(double v)
 // shift): bunch centroids stay within a few rms of the bucket centre, so the
 // variance keeps full precision, and the result depends only on the present
 // state, which makes a checkpointed run resume bit for bit.
+// The deposit phase is evaluated from the post-drift tau itself (not
+// rotated from the kick's phase), so the bin-only prologue of a resumed run
+// computes exactly the same sums as the push it replaces.
 template <int NLR>
 __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, double t, double d,
                                          double *acc)
@@ -424,56 +427,89 @@ __device__ void conv_chunk(const PrepArgs &a, int b, int chunk, double *psm)
         a.counts_clear[(size_t)b * nb + kk] = 0u;
 }
 
-// Long-range phasors advanced bunch by bunch in bucket order: rotate across
-// the gap from the previous filled bucket, record the voltage the bunch
-// sees, add the bunch's deposit qpp * c_r * sum_j exp((alpha - i wbar) tau_j).
+// Long-range phasors advanced bunch by bunch in bucket order.  Passing
+// bunch b maps the phasor x to G_b x + D_b (rotation across the gap from the
+// previous filled bucket, then the bunch's deposit D_b = qpp_b c_r S_b with
+// S_b = sum_j exp((alpha - i wbar) tau_j)), and the bunch sees G_b x.  The
+// chain of M affine maps is evaluated as a scan: each thread composes a
+// contiguous run of bunches, a Hillis-Steele scan over the 256 composed maps
+// (fixed order, so deterministic) gives each run its incoming phasor, and
+// each thread then replays its run to record what every bunch sees.
+struct cplx {
+    double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b)
+{
+    return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplx cmuladd(cplx a, cplx b, cplx c)
+{
+    return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+
 template <int NLR>
 __device__ void phasor_scan(const PrepArgs &a, double *psm)
 {
     const int tid = threadIdx.x;
-    const int chunk = 512;
-    double *sS = psm;  // [NLR][chunk][2]
-    double vr = 0.0, vi = 0.0;
-    if (tid < NLR) {
-        vr = a.phasor[2 * tid];
-        vi = a.phasor[2 * tid + 1];
-    }
-    for (int b0 = 0; b0 < a.M; b0 += chunk) {
-        const int nc = min(chunk, a.M - b0);
-        __syncthreads();
-        for (int idx = tid; idx < NLR * nc; idx += kPrepThreads) {
-            const int r = idx / nc, bb = idx - r * nc;
+    const int M = a.M;
+    const int run = (M + kPrepThreads - 1) / kPrepThreads;
+    const int b_lo = min(tid * run, M), b_hi = min(b_lo + run, M);
+    cplx *mA = reinterpret_cast<cplx *>(psm);   // [256] composed rotation
+    cplx *mB = mA + kPrepThreads;               // [256] composed offset
+#pragma unroll 1
+    for (int r = 0; r < NLR; ++r) {
+        cplx *seen = reinterpret_cast<cplx *>(a.seen) + (size_t)r * M;
+        const cplx *gap = reinterpret_cast<const cplx *>(a.gap) + (size_t)r * M;
+        const cplx *qc = reinterpret_cast<const cplx *>(a.qc) + (size_t)r * M;
+        // 1. deposits of this thread's run (stashed in `seen`) and its map
+        cplx A = {1.0, 0.0}, B = {0.0, 0.0};
+        for (int b = b_lo; b < b_hi; ++b) {
             double sr = 0.0, si = 0.0;
-            const double *p = a.partials + (size_t)(b0 + bb) * a.ntiles * kPartStride + 4 + 2 * r;
+            const double *p = a.partials + (size_t)b * a.ntiles * kPartStride + 4 + 2 * r;
             for (int t = 0; t < a.ntiles; ++t) {
                 sr += p[(size_t)t * kPartStride];
                 si += p[(size_t)t * kPartStride + 1];
             }
-            sS[(r * chunk + bb) * 2] = sr;
-            sS[(r * chunk + bb) * 2 + 1] = si;
+            const cplx D = cmul(qc[b], {sr, si});
+            seen[b] = D;
+            const cplx G = gap[b];
+            A = cmul(G, A);
+            B = cmuladd(G, B, D);
+        }
+        mA[tid] = A;
+        mB[tid] = B;
+        __syncthreads();
+        // 2. inclusive scan of the maps: map[t] <- map[t] o map[t - d]
+        for (int d = 1; d < kPrepThreads; d <<= 1) {
+            cplx nA = mA[tid], nB = mB[tid];
+            if (tid >= d) {
+                const cplx pA = mA[tid - d], pB = mB[tid - d];
+                nB = cmuladd(nA, pB, nB);
+                nA = cmul(nA, pA);
+            }
+            __syncthreads();
+            mA[tid] = nA;
+            mB[tid] = nB;
+            __syncthreads();
+        }
+        // 3. incoming phasor of this run, then replay the run
+        const cplx x0 = {a.phasor[2 * r], a.phasor[2 * r + 1]};
+        cplx x = x0;
+        if (tid > 0)
+            x = cmuladd(mA[tid - 1], x0, mB[tid - 1]);
+        for (int b = b_lo; b < b_hi; ++b) {
+            const cplx D = seen[b];
+            x = cmul(gap[b], x);
+            seen[b] = x;
+            x = {x.re + D.re, x.im + D.im};
         }
         __syncthreads();
-        if (tid < NLR) {
-            const int r = tid;
-            for (int bb = 0; bb < nc; ++bb) {
-                const size_t ix = ((size_t)r * a.M + b0 + bb) * 2;
-                const double gr = a.gap[ix], gi = a.gap[ix + 1];
-                const double nr = vr * gr - vi * gi;
-                const double ni = vr * gi + vi * gr;
-                vr = nr;
-                vi = ni;
-                a.seen[ix] = vr;
-                a.seen[ix + 1] = vi;
-                const double qr = a.qc[ix], qi = a.qc[ix + 1];
-                const double Sr = sS[(r * chunk + bb) * 2], Si = sS[(r * chunk + bb) * 2 + 1];
-                vr = vr + (qr * Sr - qi * Si);
-                vi = vi + (qr * Si + qi * Sr);
-            }
+        if (tid == kPrepThreads - 1) {
+            const cplx xe = cmuladd(mA[tid], x0, mB[tid]);
+            a.phasor[2 * r] = xe.re;
+            a.phasor[2 * r + 1] = xe.im;
         }
-    }
-    if (tid < NLR) {
-        a.phasor[2 * tid] = vr;
-        a.phasor[2 * tid + 1] = vi;
+        __syncthreads();
     }
 }
 
@@ -566,7 +602,7 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
 {
     const int blocks = a.M * conv_chunks(a) + ((a.do_scan && a.nlr > 0) ? 1 : 0);
     size_t lds = (size_t)2 * a.nbins * sizeof(double);
-    const size_t scan_lds = (size_t)a.nlr * 512 * 2 * sizeof(double);
+    const size_t scan_lds = (size_t)2 * kPrepThreads * 2 * sizeof(double);
     if (scan_lds > lds)
         lds = scan_lds;
     if (lds == 0)

@@ -148,3 +148,47 @@ def test_checkpoint_resume_bitwise(cuda):
     k.set_state(turn, seed, ph)
     m_b = k.track(20)
     assert np.array_equal(np.concatenate([m_a, m_b]), m_full)
+
+
+# Larger fills: the phasor scan over many bunches (runs of several bunches per
+# thread), a gap, an odd particle count, and edge cases of the map.
+MB_LARGE = wl.Workload(
+    name="300 bunches + gap", ring=wl.RING_R480, buckets=tuple(range(300)),
+    currents_A=tuple(1e-3 * (1 + 0.5 * np.sin(b)) for b in range(300)), N=601, turns=100, seed=9,
+    sigma_tau0=12e-12, sigma_delta0=8.6e-4, short_range=(wl.BB,), grid=(64, -76e-12, 76e-12),
+    long_range=(wl.HOM,))
+FULL_RING = MB_LARGE.with_(name="uniform 480", buckets=tuple(range(480)),
+                           currents_A=(1e-3,) * 480, N=63, seed=10)
+EDGE = {
+    "N1": MB.with_(N=1, sigma_tau0=5e-12),
+    "one_bin": wl.C1.with_(grid=(1, -60e-12, 60e-12), N=777),
+    "no_grid_lr": MB.with_(grid=None, short_range=(), N=1500),
+    "sr_off": wl.C1.with_(ring=dict(wl.RING_R480, u0_eV=0.0, tau_long_s=float("inf"),
+                                    sigma_delta=0.0), N=3000),
+    "neg_alpha": wl.C1.with_(ring=dict(wl.RING_R480, alpha_c=-6e-4), N=5000, grid=(96, -80e-12, 80e-12)),
+}
+
+
+@pytest.mark.parametrize("case", ["mb_large", "full_ring"] + sorted(EDGE))
+def test_parity_more_cases(cuda, case):
+    w = {"mb_large": MB_LARGE, "full_ring": FULL_RING}.get(case) or EDGE[case]
+    print_case("more cases", case=case, M=w.M, N=w.N)
+    o = make_oracle(w, init=False)
+    g = make_tracker(w, init=False)
+    set_same_particles(w, [o, g], w.N)
+    o.track(1)
+    g.track(1)
+    for b in range(0, w.M, max(1, w.M // 17)):
+        to, do = o.get_particles(b)
+        tg, dg = g.get_particles(b)
+        et, ed = coord_excess(tg, to), coord_excess(dg, do)
+        assert et <= COORD_RTOL and ed <= COORD_RTOL, (b, et, ed)
+    mo = o.track(60)
+    mg = g.track(60)
+    if w.N > 1:
+        assert moment_excess(mg, mo) <= MOMENT_RTOL
+    else:  # one particle: rms is zero, compare the coordinates themselves
+        scale = np.array([w.sigma_tau0, w.sigma_delta0])
+        assert np.max(np.abs(mg[..., :2] - mo[..., :2]) / scale) <= MOMENT_RTOL
+    if w.long_range:
+        assert np.allclose(g.get_state()[2], o.get_state()[2], rtol=1e-9, atol=0)
