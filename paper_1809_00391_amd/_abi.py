@@ -7,7 +7,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmbt.so")
+# MBT_LIBRARY may point at another build of the same library (A/B runs).
+LIB_PATH = os.environ.get("MBT_LIBRARY") or os.path.join(_HERE, "libmbt.so")
 
 MBT_OK = 0
 MBT_EINVAL = -1

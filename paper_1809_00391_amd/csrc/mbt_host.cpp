@@ -51,7 +51,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Offsets of every workspace region for a given job shape.
 struct Layout {
-    size_t W, V, counts, partials, seen, gap, qc, phasor, qpp, stream, status, mom, prof;
+    size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, status, mom, prof;
     size_t total;
     int ring_turns, prof_slots, ntiles;
     int64_t ld;
@@ -79,6 +79,7 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     L.V = take((size_t)M * nbx * sizeof(double));
     L.counts = take((size_t)2 * M * nbx * sizeof(uint32_t));
     L.partials = take((size_t)M * L.ntiles * kPartStride * sizeof(double));
+    L.S = take((size_t)nl * M * 2 * sizeof(double));
     L.seen = take((size_t)nl * M * 2 * sizeof(double));
     L.gap = take((size_t)nl * M * 2 * sizeof(double));
     L.qc = take((size_t)nl * M * 2 * sizeof(double));
@@ -256,6 +257,7 @@ PrepArgs prep_args(const mbt_ctx *c, bool conv, bool scan, double *mom_out)
     p.V = c->w<double>(c->L.V);
     p.gap = c->w<double>(c->L.gap);
     p.qc = c->w<double>(c->L.qc);
+    p.S = c->w<double>(c->L.S);
     p.phasor = c->w<double>(c->L.phasor);
     p.seen = c->w<double>(c->L.seen);
     p.status = c->w<uint32_t>(c->L.status);

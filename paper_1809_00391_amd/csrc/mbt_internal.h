@@ -75,6 +75,7 @@ struct PrepArgs {
     double *V;                // [M][nbins]
     const double *gap;        // [nlr][M][2] rotation into bunch b's bucket
     const double *qc;         // [nlr][M][2] qpp_b * c_r
+    double *S;                // [nlr][M][2] deposit sums of each bunch
     double *phasor;           // [nlr][2] state
     double *seen;             // [nlr][M][2]
     uint32_t *status;         // bit 0: non-finite moment

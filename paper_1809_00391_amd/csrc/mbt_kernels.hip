@@ -1,12 +1,15 @@
 // mbt_kernels.hip -- HIP kernels of the longitudinal multi-bunch tracker for
 // CDNA4 (gfx950).
 //
-// One turn is two launches on the caller's stream:
-//   k_prep  (M x ceil(nbins/64) [+1] workgroups): finishes the previous
-//           push's per-bunch sums (moments, Sec. 2.4), builds each bunch's
-//           binned wake potential from its line density (Sec. 2.3), and
-//           advances the long-range phasors through the bunches in bucket
-//           order (one extra workgroup, as a scan of affine maps).
+// One turn is two launches on the caller's stream (three with long-range
+// resonators):
+//   k_prep  (M x ceil(nbins/64) workgroups): finishes the previous push's
+//           per-bunch sums (moments, Sec. 2.4, and long-range deposits) and
+//           builds each bunch's binned wake potential from its line density
+//           (Sec. 2.3);
+//   k_scan  (one workgroup, with long-range resonators): advances the
+//           long-range phasors through the bunches in bucket order as a scan
+//           of affine maps.
 //   k_push  (tiles x M workgroups): the single-particle map of every particle
 //           (Sec. 2.2: Eq. 1 kick with RF, harmonic cavity and U0; Eq. 6
 //           short-range kick of the particle's bin; long-range kick; Eq. 5
@@ -200,14 +203,37 @@ int push_nsub(int nbins)
     return 1;
 }
 
-// One pair of neighbouring particles j0, j0 + 1 (the second only if `two`).
+// Map and epilogue of the pair (t0, d0), (t1, d1) = particles 2p, 2p + 1
+// (the second only if `two`); the pushed coordinates are returned in place.
+template <int NLR, bool PUSH>
+__device__ __forceinline__ void pair_compute(const PushArgs &a, const double *Vs,
+                                             const double (&seen)[NLR > 0 ? NLR : 1][2],
+                                             uint32_t *hist_w, uint32_t p, uint32_t stream,
+                                             bool two, double &t0, double &t1, double &d0,
+                                             double &d1, double *acc)
+{
+    const MapConst &c = a.c;
+    if (PUSH) {
+        double z0 = 0.0, z1 = 0.0;
+        if (c.noise_on)
+            normal_pair(p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
+        double s0, c0, s1, c1;
+        rf_phase(c.w_rf * t0, c.w_rf * t1, s0, c0, s1, c1);
+        kick_drift<NLR>(c, Vs, seen, s0, c0, z0, t0, d0);
+        kick_drift<NLR>(c, Vs, seen, s1, c1, z1, t1, d1);
+    }
+    epilogue<NLR>(c, hist_w, t0, d0, acc);
+    if (two)
+        epilogue<NLR>(c, hist_w, t1, d1, acc);
+}
+
+// One pair with bounds handling (a bunch's last tile).
 template <int NLR, bool PUSH>
 __device__ __forceinline__ void pair_step(const PushArgs &a, const double *Vs,
                                           const double (&seen)[NLR > 0 ? NLR : 1][2],
                                           uint32_t *hist_w, double *tau, double *del, uint32_t p,
                                           uint32_t stream, bool two, double *acc)
 {
-    const MapConst &c = a.c;
     const uint32_t j0 = 2u * p;
     double t0, t1 = 0.0, d0, d1 = 0.0;
     if (two) {
@@ -218,14 +244,8 @@ __device__ __forceinline__ void pair_step(const PushArgs &a, const double *Vs,
         t0 = tau[j0];
         d0 = del[j0];
     }
+    pair_compute<NLR, PUSH>(a, Vs, seen, hist_w, p, stream, two, t0, t1, d0, d1, acc);
     if (PUSH) {
-        double z0 = 0.0, z1 = 0.0;
-        if (c.noise_on)
-            normal_pair(p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
-        double s0, c0, s1, c1;
-        rf_phase(c.w_rf * t0, c.w_rf * t1, s0, c0, s1, c1);
-        kick_drift<NLR>(c, Vs, seen, s0, c0, z0, t0, d0);
-        kick_drift<NLR>(c, Vs, seen, s1, c1, z1, t1, d1);
         if (two) {
             *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
             *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
@@ -234,9 +254,6 @@ __device__ __forceinline__ void pair_step(const PushArgs &a, const double *Vs,
             del[j0] = d0;
         }
     }
-    epilogue<NLR>(c, hist_w, t0, d0, acc);
-    if (two)
-        epilogue<NLR>(c, hist_w, t1, d1, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,10 +304,28 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
     // Indices within the bunch fit 32 bits (N <= 2^32, so a pair index < 2^31).
     const uint32_t pair0 = (uint32_t)tile * (kPushThreads * kPairsPerThread);
     if ((int64_t)(pair0 + kPushThreads * kPairsPerThread) * 2 <= a.N) {
+        // Full tile: the next pair's coordinates are loaded before the
+        // current pair is computed, so each wavefront keeps a load in flight.
+        uint32_t p = pair0 + (uint32_t)tid;
+        double2 tv = *reinterpret_cast<const double2 *>(tau + 2u * p);
+        double2 dv = *reinterpret_cast<const double2 *>(del + 2u * p);
 #pragma unroll 1
-        for (int it = 0; it < kPairsPerThread; ++it)
-            pair_step<NLR, PUSH>(a, Vs, seen, hist_w, tau, del,
-                                 pair0 + (uint32_t)(it * kPushThreads + tid), stream, true, acc);
+        for (int it = 0; it < kPairsPerThread; ++it) {
+            double2 tn = tv, dn = dv;
+            if (it + 1 < kPairsPerThread) {
+                tn = *reinterpret_cast<const double2 *>(tau + 2u * (p + kPushThreads));
+                dn = *reinterpret_cast<const double2 *>(del + 2u * (p + kPushThreads));
+            }
+            double t0 = tv.x, t1 = tv.y, d0 = dv.x, d1 = dv.y;
+            pair_compute<NLR, PUSH>(a, Vs, seen, hist_w, p, stream, true, t0, t1, d0, d1, acc);
+            if (PUSH) {
+                *reinterpret_cast<double2 *>(tau + 2u * p) = make_double2(t0, t1);
+                *reinterpret_cast<double2 *>(del + 2u * p) = make_double2(d0, d1);
+            }
+            tv = tn;
+            dv = dn;
+            p += kPushThreads;
+        }
     } else {
         const uint32_t n_part = (uint32_t)(a.N - 1);  // last particle index
 #pragma unroll 1
@@ -338,35 +373,42 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
 // ---------------------------------------------------------------------------
 constexpr int kConvOut = 64;
 
-// Moments of bunch b from the tile sums of the last push (Sec. 2.4).
-__device__ void finish_moments(const PrepArgs &a, int b)
+// Moments of bunch b from the tile sums of the last push (Sec. 2.4), and
+// the bunch's long-range deposit sums S[r][b] = sum_j exp((alpha - i wbar) tau_j).
+template <int NLR>
+__device__ void finish_sums(const PrepArgs &a, int b)
 {
-    __shared__ double sred[kPrepThreads / 64][4];
+    constexpr int NP = 4 + 2 * NLR;
+    __shared__ double sred[kPrepThreads / 64][NP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+        s[i] = 0.0;
     for (int t = tid; t < a.ntiles; t += kPrepThreads) {
         const double *p = a.partials + ((size_t)b * a.ntiles + t) * kPartStride;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NP; ++i)
             s[i] += p[i];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NP; ++i) {
         const double v = wave_sum(s[i]);
         if (lane == 0)
             sred[wave][i] = v;
     }
     __syncthreads();
+    if (tid < NP) {
+        double tot = sred[0][tid];
+        for (int w = 1; w < kPrepThreads / 64; ++w)
+            tot += sred[w][tid];
+        sred[0][tid] = tot;
+    }
+    __syncthreads();
     if (tid == 0) {
-        double tot[4];
-        for (int i = 0; i < 4; ++i) {
-            tot[i] = sred[0][i];
-            for (int w = 1; w < kPrepThreads / 64; ++w)
-                tot[i] += sred[w][i];
-        }
         const double invN = 1.0 / (double)a.N;
-        const double mt = tot[0] * invN, md = tot[2] * invN;
-        const double vt = tot[1] * invN - mt * mt, vd = tot[3] * invN - md * md;
+        const double mt = sred[0][0] * invN, md = sred[0][2] * invN;
+        const double vt = sred[0][1] * invN - mt * mt, vd = sred[0][3] * invN - md * md;
         const double rms_t = sqrt(vt > 0.0 ? vt : 0.0), rms_d = sqrt(vd > 0.0 ? vd : 0.0);
         if (a.mom_out) {
             a.mom_out[4 * b + 0] = mt;
@@ -377,6 +419,8 @@ __device__ void finish_moments(const PrepArgs &a, int b)
         if (!isfinite(mt) || !isfinite(md) || !isfinite(vt) || !isfinite(vd))
             atomicOr(a.status, 1u);
     }
+    if (tid < 2 * NLR)
+        a.S[((size_t)(tid >> 1) * a.M + b) * 2 + (tid & 1)] = sred[0][4 + tid];
 }
 
 // Bins [k0, k1) of bunch b's wake potential (Sec. 2.3):
@@ -448,33 +492,25 @@ __device__ __forceinline__ cplx cmuladd(cplx a, cplx b, cplx c)
 }
 
 template <int NLR>
-__device__ void phasor_scan(const PrepArgs &a, double *psm)
+__global__ __launch_bounds__(kPrepThreads) void k_scan(const PrepArgs a)
 {
+    __shared__ cplx mA[kPrepThreads], mB[kPrepThreads];  // composed maps
     const int tid = threadIdx.x;
     const int M = a.M;
     const int run = (M + kPrepThreads - 1) / kPrepThreads;
     const int b_lo = min(tid * run, M), b_hi = min(b_lo + run, M);
-    cplx *mA = reinterpret_cast<cplx *>(psm);   // [256] composed rotation
-    cplx *mB = mA + kPrepThreads;               // [256] composed offset
 #pragma unroll 1
     for (int r = 0; r < NLR; ++r) {
         cplx *seen = reinterpret_cast<cplx *>(a.seen) + (size_t)r * M;
         const cplx *gap = reinterpret_cast<const cplx *>(a.gap) + (size_t)r * M;
         const cplx *qc = reinterpret_cast<const cplx *>(a.qc) + (size_t)r * M;
-        // 1. deposits of this thread's run (stashed in `seen`) and its map
+        const cplx *S = reinterpret_cast<const cplx *>(a.S) + (size_t)r * M;
+        // 1. this thread's run: compose x -> G_b x + qc_b S_b over its bunches
         cplx A = {1.0, 0.0}, B = {0.0, 0.0};
         for (int b = b_lo; b < b_hi; ++b) {
-            double sr = 0.0, si = 0.0;
-            const double *p = a.partials + (size_t)b * a.ntiles * kPartStride + 4 + 2 * r;
-            for (int t = 0; t < a.ntiles; ++t) {
-                sr += p[(size_t)t * kPartStride];
-                si += p[(size_t)t * kPartStride + 1];
-            }
-            const cplx D = cmul(qc[b], {sr, si});
-            seen[b] = D;
             const cplx G = gap[b];
             A = cmul(G, A);
-            B = cmuladd(G, B, D);
+            B = cmuladd(G, B, cmul(qc[b], S[b]));
         }
         mA[tid] = A;
         mB[tid] = B;
@@ -498,9 +534,9 @@ __device__ void phasor_scan(const PrepArgs &a, double *psm)
         if (tid > 0)
             x = cmuladd(mA[tid - 1], x0, mB[tid - 1]);
         for (int b = b_lo; b < b_hi; ++b) {
-            const cplx D = seen[b];
             x = cmul(gap[b], x);
             seen[b] = x;
+            const cplx D = cmul(qc[b], S[b]);
             x = {x.re + D.re, x.im + D.im};
         }
         __syncthreads();
@@ -524,16 +560,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
     extern __shared__ double psm[];
     const int nchunks = conv_chunks(a);
     const int blk = blockIdx.x;
-    if (blk < a.M * nchunks) {
-        const int b = blk / nchunks, chunk = blk - b * nchunks;
-        if (chunk == 0)
-            finish_moments(a, b);
-        if (a.do_conv)
-            conv_chunk(a, b, chunk, psm);
-        return;
-    }
-    if (a.do_scan && NLR > 0)
-        phasor_scan<NLR>(a, psm);
+    const int b = blk / nchunks, chunk = blk - b * nchunks;
+    if (chunk == 0)
+        finish_sums<NLR>(a, b);
+    if (a.do_conv)
+        conv_chunk(a, b, chunk, psm);
 }
 
 // ---------------------------------------------------------------------------
@@ -600,11 +631,8 @@ hipError_t launch_push(const PushArgs &a, int nlr, bool push, hipStream_t s)
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
 {
-    const int blocks = a.M * conv_chunks(a) + ((a.do_scan && a.nlr > 0) ? 1 : 0);
+    const int blocks = a.M * conv_chunks(a);
     size_t lds = (size_t)2 * a.nbins * sizeof(double);
-    const size_t scan_lds = (size_t)2 * kPrepThreads * 2 * sizeof(double);
-    if (scan_lds > lds)
-        lds = scan_lds;
     if (lds == 0)
         lds = 16;
     switch (a.nlr) {
@@ -613,6 +641,16 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
     case 2: hipLaunchKernelGGL((k_prep<2>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
     case 3: hipLaunchKernelGGL((k_prep<3>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
     case 4: hipLaunchKernelGGL((k_prep<4>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.do_scan || a.nlr == 0)
+        return e;
+    switch (a.nlr) {
+    case 1: hipLaunchKernelGGL((k_scan<1>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_scan<2>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_scan<3>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_scan<4>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
