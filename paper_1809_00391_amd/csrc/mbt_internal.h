@@ -8,8 +8,14 @@
 namespace mbt {
 
 constexpr int kMaxLR = 4;            // long-range resonators
-constexpr int kPushThreads = 256;    // 4 wavefronts of 64
-constexpr int kPairsPerThread = 8;   // pairs of particles per thread per tile
+#ifndef MBT_PUSH_THREADS
+#define MBT_PUSH_THREADS 256
+#endif
+#ifndef MBT_PAIRS_PER_THREAD
+#define MBT_PAIRS_PER_THREAD 8
+#endif
+constexpr int kPushThreads = MBT_PUSH_THREADS;         // wavefronts of 64
+constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // particle pairs per thread per tile
 constexpr int kTile = kPushThreads * 2 * kPairsPerThread;  // particles per tile
 constexpr int kPartStride = 4 + 2 * kMaxLR;  // doubles per tile partial
 constexpr int kPrepThreads = 256;
