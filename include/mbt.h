@@ -195,7 +195,8 @@ int mbt_set_particles(mbt_ctx *ctx, int32_t bunch, const double *tau, const doub
 /* Copy N coordinates of bunch `bunch` out; synchronises the bound stream. */
 int mbt_get_particles(mbt_ctx *ctx, int32_t bunch, double *tau, double *delta, int32_t where);
 
-/* Track nturns turns from the stored turn counter (so a checkpoint resumes).
+/* Track nturns turns (nturns < 2^31) from the stored turn counter (so a
+ * checkpoint resumes).
  *   out:    host array [nturns][M] of moments after each turn (may be NULL)
  *   counts: host array [ceil(nturns/stride)][M][nbins] of bin counts of the
  *           state after turns 0, stride, 2*stride, ... of this call (may be
@@ -203,7 +204,9 @@ int mbt_get_particles(mbt_ctx *ctx, int32_t bunch, double *tau, double *delta, i
  * Each turn, for every bunch in bucket order: the kick (RF + harmonic cavity
  * - U0 - short-range wake of the bin - long-range voltage), damping and
  * quantum excitation with noise keyed by (seed, turn, stream ordinal,
- * particle/2), then the drift (Sec. 2.2-2.4).  Blocks until done.
+ * particle/2), then the drift (Sec. 2.2-2.4).  Three kernel launches per
+ * turn on the bound stream; the host does not wait on the device inside the
+ * loop except to copy a full output ring out.  Blocks until done.
  * MBT_ENUMERIC if a bunch moment became non-finite. */
 int mbt_track(mbt_ctx *ctx, int64_t nturns, mbt_moments *out, uint32_t *counts,
               int32_t stride);
@@ -227,14 +230,66 @@ int mbt_get_state(mbt_ctx *ctx, int64_t *turn, uint64_t *seed, double *phasors);
 int mbt_set_state(mbt_ctx *ctx, int64_t turn, uint64_t seed, const double *phasors);
 
 /* Kernel timing for measurement.  With every > 0, mbt_track records HIP
- * events on the bound stream around the push launch and the between-turn
- * launch of every `every`-th turn (at most 4096 of each per call) and adds
- * their elapsed times to running totals; every = 0 switches it off and
+ * events on the bound stream around the push launch and around the
+ * between-turn launches (phasor scan and prep) of every `every`-th turn (at
+ * most 4096 turns per call) and adds their elapsed times to running totals; every = 0 switches it off and
  * clears the totals.  mbt_get_timing returns the totals in milliseconds and
  * the number of timed launches (any pointer may be NULL). */
 int mbt_set_timing(mbt_ctx *ctx, int32_t every);
 int mbt_get_timing(const mbt_ctx *ctx, double *push_ms, int64_t *push_launches,
                    double *prep_ms, int64_t *prep_launches);
+
+/* Launch shape of the push: nsub LDS sub-histograms per workgroup (0: a
+ * default from nbins) and push_grid persistent workgroups (0: one workgroup
+ * per tile of 4096 particles).  Neither changes any result bit: histograms
+ * are integer sums and each tile's partial sums keep their order.
+ * MBT_EINVAL if the LDS image of the push would exceed 64 KiB. */
+int mbt_set_launch(mbt_ctx *ctx, int32_t nsub, int32_t push_grid);
+
+/* ---- Batches -------------------------------------------------------------
+ * A batch advances several bound jobs (contexts on one device) together:
+ * each turn is three launches that cover every bunch of every job -- the
+ * phasor scan of all jobs, the push of all tiles (one launch per distinct
+ * long-range resonator count), the prep of all bunches.  Each job keeps its
+ * own seed, turn counter, workspace and reduction layout, so its results are
+ * bit for bit those of tracking it alone with mbt_track.  A job in a batch
+ * must not be tracked on its own or rebound while the batch exists; destroy
+ * the batch first.
+ *
+ * mbt_batch_query_bytes: device bytes of the batch's descriptor and item
+ * tables (caller-owned, 256-byte aligned).  mbt_batch_create: builds the
+ * tables in d_work on hip_stream (NULL: default stream) and creates a private
+ * stream for graph capture.  MBT_EINVAL on duplicate jobs, jobs on different
+ * devices, njobs outside [1, 65535]; MBT_ESTATE if a job is not bound. */
+typedef struct mbt_batch mbt_batch;
+int mbt_batch_query_bytes(mbt_ctx *const *jobs, int32_t njobs, size_t *work_bytes);
+int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t work_bytes,
+                     void *hip_stream, mbt_batch **out);
+void mbt_batch_destroy(mbt_batch *batch);
+const char *mbt_batch_last_error(const mbt_batch *batch);
+
+/* graph_turns > 1: turns are captured once as a HIP graph of that many turns
+ * (at most each job's moment ring and profile ring allow) and replayed; the
+ * turn counter lives in device memory, so a replay needs no parameter
+ * update.  0 or 1: launches are issued turn by turn.  autotune = 1: on the
+ * first call with enough turns, the push's sub-histogram count and
+ * persistent grid are timed over real turns and the fastest kept, cached per
+ * process by (resonator count, bins, item count); these choices change no
+ * result bit. */
+int mbt_batch_configure(mbt_batch *batch, int32_t graph_turns, int32_t autotune);
+
+/* Push groups of the batch and their present launch shape: per group the
+ * long-range resonator count, sub-histograms and workgroups (arrays of at
+ * least MBT_MAX_LONG_RANGE + 1 entries; any may be NULL except ngroups). */
+int mbt_batch_launch_info(const mbt_batch *batch, int32_t *ngroups, int32_t *nlr, int32_t *nsub,
+                          int32_t *grid);
+
+/* Track nturns turns of every job.  out[j] (host [nturns][M_j], or NULL) and
+ * counts[j] (host [ceil(nturns/stride[j])][M_j][nbins_j], or NULL) as in
+ * mbt_track; out, counts and stride may themselves be NULL.  Blocks until
+ * done.  MBT_ENUMERIC names the first job with a non-finite moment. */
+int mbt_batch_track(mbt_batch *batch, int64_t nturns, mbt_moments *const *out,
+                    uint32_t *const *counts, const int32_t *stride);
 
 /* Raw Philox-4x32-10 blocks on the device (the generator behind the noise,
  * Salmon et al. SC'11): out[i][0..3] = philox(ctr[i][0..3], key), for

@@ -74,6 +74,16 @@ SIGNATURES = {
     "mbt_set_timing": (C.c_int, [_ctx, C.c_int32]),
     "mbt_get_timing": (C.c_int, [_ctx, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                  _P(C.c_int64)]),
+    "mbt_set_launch": (C.c_int, [_ctx, C.c_int32, C.c_int32]),
+    "mbt_batch_query_bytes": (C.c_int, [C.c_void_p, C.c_int32, _P(C.c_size_t)]),
+    "mbt_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                   _P(C.c_void_p)]),
+    "mbt_batch_destroy": (None, [C.c_void_p]),
+    "mbt_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "mbt_batch_configure": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "mbt_batch_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), C.c_void_p, C.c_void_p,
+                                        C.c_void_p]),
+    "mbt_batch_track": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbt_philox4x32_10": (C.c_int, [C.c_int64, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p,
                                     C.c_void_p]),
 }

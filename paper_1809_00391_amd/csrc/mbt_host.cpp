@@ -15,6 +15,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -49,11 +51,22 @@ bool res_valid(const mbt_resonator &r)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int floor_pow2(size_t x)
+{
+    int p = 1;
+    while ((size_t)p * 2 <= x && p < (1 << 30))
+        p *= 2;
+    return p;
+}
+
+constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS of one push workgroup
+
 // Offsets of every workspace region for a given job shape.
 struct Layout {
-    size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, status, mom, prof;
+    size_t desc, items_push, items_prep, clock, status;
+    size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, mom, prof;
     size_t total;
-    int ring_turns, prof_slots, ntiles;
+    int mom_slots, prof_slots, ntiles, nchunks;
     int64_t ld;
     size_t state_bytes;
 };
@@ -64,10 +77,12 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     const int nbx = std::max(nb, 1);
     L.ld = (N + kRowAlign - 1) / kRowAlign * kRowAlign;
     L.ntiles = (int)((N + kTile - 1) / kTile);
+    L.nchunks = conv_chunks(nb);
+    // output rings: powers of two, about 16 MB each at most
     const size_t moment_row = (size_t)M * 4 * sizeof(double);
-    L.ring_turns = (int)std::max<size_t>(16, std::min<size_t>(1024, (16u << 20) / moment_row));
+    L.mom_slots = floor_pow2(std::max<size_t>(16, std::min<size_t>(1024, (16u << 20) / moment_row)));
     const size_t prof_row = (size_t)M * nbx * sizeof(uint32_t);
-    L.prof_slots = (int)std::max<size_t>(1, std::min<size_t>(64, (16u << 20) / prof_row));
+    L.prof_slots = floor_pow2(std::max<size_t>(1, std::min<size_t>(64, (16u << 20) / prof_row)));
     const int nl = std::max(nlr, 1);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -75,6 +90,11 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
         o = align256(o + bytes);
         return at;
     };
+    L.desc = take(sizeof(JobDesc));
+    L.items_push = take((size_t)M * L.ntiles * sizeof(Item));
+    L.items_prep = take((size_t)M * L.nchunks * sizeof(Item));
+    L.clock = take(sizeof(uint32_t));
+    L.status = take(sizeof(uint32_t));
     L.W = take((size_t)nbx * sizeof(double));
     L.V = take((size_t)M * nbx * sizeof(double));
     L.counts = take((size_t)2 * M * nbx * sizeof(uint32_t));
@@ -86,23 +106,60 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     L.phasor = take((size_t)nl * 2 * sizeof(double));
     L.qpp = take((size_t)M * sizeof(double));
     L.stream = take((size_t)M * sizeof(uint32_t));
-    L.status = take(sizeof(uint32_t));
-    L.mom = take((size_t)L.ring_turns * moment_row);
+    L.mom = take((size_t)L.mom_slots * moment_row);
     L.prof = take((size_t)L.prof_slots * prof_row);
     L.total = o;
     L.state_bytes = (size_t)2 * M * (size_t)L.ld * sizeof(double);
     return L;
 }
 
-// One pending device->pinned->caller copy.
-struct Pending {
+// Default sub-histograms per push workgroup: several copies spread the LDS
+// atomics of a wavefront over more banks when they fit.
+int default_nsub(int nbins)
+{
+    if (nbins <= 0)
+        return 0;
+    int n = nbins <= 1024 ? 4 : (nbins <= 2048 ? 2 : 1);
+    while (n > 1 && push_lds_bytes(nbins, n) > kLdsLimit)
+        n /= 2;
+    return n;
+}
+
+// A device ring of `slots` rows (power of two) that a kernel fills row by
+// row, copied out to a host array through a pinned buffer of the ring's size.
+// Rows are numbered from the start of the call; row r sits in slot
+// r & (slots - 1).  Before work that writes rows [written, written + n) is
+// enqueued, rows that would be overwritten are copied out first.
+struct RingOut {
+    const unsigned char *dev = nullptr;
+    size_t row_bytes = 0;
+    int slots = 0;
+    unsigned char *dst = nullptr;  // host row 0 of this call (NULL: not wanted)
+    int64_t flushed = 0, written = 0;
+    // staging: the pinned copy of the ring and the event its last copy recorded
+    unsigned char *pin = nullptr;
     hipEvent_t ev = nullptr;
-    void *dst = nullptr;
-    size_t bytes = 0;
-    bool busy = false;
+    struct Piece { size_t pin_off; int64_t row; int64_t rows; };
+    std::vector<Piece> pending;
 };
 
 }  // namespace
+
+// Event pairs around launches, for measurement only.
+struct Timer {
+    static constexpr int kMax = 4096;
+    int every = 0;
+    std::vector<hipEvent_t> ev[2];  // [0]: push, [1]: between-turn (scan + prep)
+    int n[2] = {0, 0};              // pairs recorded since the last collect
+    double ms[2] = {0.0, 0.0};
+    int64_t launches[2] = {0, 0};
+};
+
+// Pinned host image of what the host writes into a job's workspace.
+struct Mirror {
+    JobDesc desc;
+    uint32_t clock;
+};
 
 struct mbt_ctx {
     // parameters
@@ -124,20 +181,15 @@ struct mbt_ctx {
     unsigned char *work = nullptr;
     hipStream_t stream_h = nullptr;
     int device = 0;
-    // pinned staging (two buffers each for moments and profiles)
-    void *pin_mom[2] = {nullptr, nullptr};
-    void *pin_prof[2] = {nullptr, nullptr};
-    Pending pend_mom[2], pend_prof[2];
-    // kernel timing (measurement only)
-    int timing_every = 0;
-    std::vector<hipEvent_t> ev_push, ev_prep;  // start/end pairs
-    int n_push_ev = 0, n_prep_ev = 0;          // pairs recorded in this call
-    double push_ms = 0.0, prep_ms = 0.0;
-    int64_t push_launches = 0, prep_launches = 0;
+    Mirror *mirror = nullptr;  // pinned
+    RingOut mom, prof;         // pinned staging of the output rings
+    // launch shape (neither changes a result bit)
+    int nsub = 0, push_grid = 0;
+    Timer timer;
     // run state
     bool have_particles = false;
-    bool dirty = true;  // partials/histogram do not describe the present state
-    int64_t turn = 0;
+    bool dirty = true;  // tile sums, histogram and wake potential do not describe the present state
+    int64_t turn = 0;   // turns completed; the device clock holds turn - 1
     uint64_t seed = 0;
     char err[512] = "";
 
@@ -146,9 +198,13 @@ struct mbt_ctx {
     int nlr() const { return (int)lr.size(); }
 };
 
+struct mbt_batch;
+
 namespace {
 
-int fail(mbt_ctx *c, int code, const char *fmt, ...)
+// Record a message on a context or batch (anything with an `err` buffer).
+template <class C>
+int fail(C *c, int code, const char *fmt, ...)
 {
     if (c) {
         va_list ap;
@@ -212,182 +268,334 @@ MapConst map_const(const mbt_ctx *c)
     return m;
 }
 
-PushArgs push_args(const mbt_ctx *c, bool for_push)
+// Descriptor of a bound job for a call that starts at turn `base` and records
+// a profile every `prof_stride`-th turn (0: none).
+JobDesc job_desc(const mbt_ctx *c, uint32_t base, int prof_stride)
 {
-    PushArgs a{};
-    a.c = map_const(c);
-    a.tau = c->tau;
-    a.delta = c->delta;
-    a.ld = c->L.ld;
-    a.N = c->N;
-    a.M = c->M;
-    a.ntiles = c->L.ntiles;
-    a.nsub = push_nsub(c->nbins());
-    a.V = c->w<double>(c->L.V);
-    a.seen = c->w<double>(c->L.seen);
-    a.stream = c->w<uint32_t>(c->L.stream);
-    const int64_t cbuf = for_push ? ((c->turn + 1) & 1) : (c->turn & 1);
-    a.counts_out = c->w<uint32_t>(c->L.counts) + (size_t)cbuf * c->M * std::max(c->nbins(), 1);
-    a.partials = c->w<double>(c->L.partials);
-    a.key0 = (uint32_t)c->seed;
-    a.key1 = (uint32_t)(c->seed >> 32);
-    a.turn = (uint32_t)c->turn;
-    return a;
+    JobDesc d{};
+    d.c = map_const(c);
+    d.tau = c->tau;
+    d.delta = c->delta;
+    d.ld = c->L.ld;
+    d.N = c->N;
+    d.M = c->M;
+    d.ntiles = c->L.ntiles;
+    d.nsub = c->nsub;
+    d.nlr = c->nlr();
+    d.mom_slots = c->L.mom_slots;
+    d.prof_stride = prof_stride;
+    d.prof_slots = c->L.prof_slots;
+    d.base = base;
+    d.key0 = (uint32_t)c->seed;
+    d.key1 = (uint32_t)(c->seed >> 32);
+    d.W = c->w<double>(c->L.W);
+    d.qpp = c->w<double>(c->L.qpp);
+    d.gap = c->w<double>(c->L.gap);
+    d.qc = c->w<double>(c->L.qc);
+    d.stream = c->w<uint32_t>(c->L.stream);
+    d.V = c->w<double>(c->L.V);
+    d.partials = c->w<double>(c->L.partials);
+    d.S = c->w<double>(c->L.S);
+    d.seen = c->w<double>(c->L.seen);
+    d.phasor = c->w<double>(c->L.phasor);
+    d.mom_ring = c->w<double>(c->L.mom);
+    d.counts = c->w<uint32_t>(c->L.counts);
+    d.prof_ring = c->w<uint32_t>(c->L.prof);
+    d.status = c->w<uint32_t>(c->L.status);
+    d.clock = c->w<uint32_t>(c->L.clock);
+    return d;
 }
 
-// prep(n) at the present turn n: moments of the state at the start of turn n
-// (into mom_out if given), wake potential, phasor scan.
-PrepArgs prep_args(const mbt_ctx *c, bool conv, bool scan, double *mom_out)
+// Push items of a job: (job, bunch, tile), bunch-major.
+void push_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 {
-    PrepArgs p{};
-    const int nbx = std::max(c->nbins(), 1);
-    p.M = c->M;
-    p.ntiles = c->L.ntiles;
-    p.N = c->N;
-    p.nbins = c->nbins();
-    p.nlr = c->nlr();
-    p.do_conv = (conv && c->sr_on) ? 1 : 0;
-    p.do_scan = (scan && c->nlr() > 0) ? 1 : 0;
-    p.partials = c->w<double>(c->L.partials);
-    p.mom_out = mom_out;
-    p.counts_in = c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * nbx;
-    p.counts_clear = c->w<uint32_t>(c->L.counts) + (size_t)((c->turn + 1) & 1) * c->M * nbx;
-    p.W = c->w<double>(c->L.W);
-    p.qpp = c->w<double>(c->L.qpp);
-    p.V = c->w<double>(c->L.V);
-    p.gap = c->w<double>(c->L.gap);
-    p.qc = c->w<double>(c->L.qc);
-    p.S = c->w<double>(c->L.S);
-    p.phasor = c->w<double>(c->L.phasor);
-    p.seen = c->w<double>(c->L.seen);
-    p.status = c->w<uint32_t>(c->L.status);
-    return p;
+    for (int b = 0; b < c->M; ++b)
+        for (int t = 0; t < c->L.ntiles; ++t)
+            out.push_back(Item{(uint16_t)job, (uint16_t)b, (uint32_t)t});
 }
 
-// Bin-only pass over the present state: histogram, deposits and moment sums
-// that the next prep consumes.
-int prologue(mbt_ctx *c)
+// Prep items of a job: (job, bunch, 64-bin chunk).
+void prep_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 {
+    for (int b = 0; b < c->M; ++b)
+        for (int k = 0; k < c->L.nchunks; ++k)
+            out.push_back(Item{(uint16_t)job, (uint16_t)b, (uint32_t)k});
+}
+
+// Launch tables of a set of jobs whose descriptors and item lists are in
+// device memory.  Push items are grouped by the number of long-range
+// resonators (a template parameter of the push).
+struct Group {
+    int item0 = 0, nitems = 0, nlr = 0, nbins_max = 0, nsub_max = 0, grid = 0;
+};
+struct Engine {
+    const JobDesc *jobs = nullptr;
+    const Item *push_items = nullptr;
+    const Item *prep_items = nullptr;
+    int njobs = 0, nprep = 0, nlr_max = 0, nbins_max = 0;
+    std::vector<Group> groups;
+};
+
+PushLaunch push_launch(const Engine &e, const Group &g)
+{
+    PushLaunch l{};
+    l.jobs = e.jobs;
+    l.items = e.push_items + g.item0;
+    l.nitems = g.nitems;
+    l.nlr = g.nlr;
+    l.nbins_max = g.nbins_max;
+    l.nsub_max = g.nsub_max;
+    l.grid = g.grid > 0 ? std::min(g.grid, g.nitems) : g.nitems;
+    return l;
+}
+
+hipError_t enqueue_push(const Engine &e, bool push, hipStream_t s)
+{
+    for (const Group &g : e.groups) {
+        hipError_t r = launch_push(push_launch(e, g), push, s);
+        if (r != hipSuccess)
+            return r;
+    }
+    return hipSuccess;
+}
+
+hipError_t enqueue_prep(const Engine &e, hipStream_t s)
+{
+    PrepLaunch l{};
+    l.jobs = e.jobs;
+    l.items = e.prep_items;
+    l.nitems = e.nprep;
+    l.nlr_max = e.nlr_max;
+    l.nbins_max = e.nbins_max;
+    l.do_conv = 1;
+    return launch_prep(l, s);
+}
+
+hipError_t enqueue_scan(const Engine &e, hipStream_t s)
+{
+    ScanLaunch l{};
+    l.jobs = e.jobs;
+    l.njobs = e.njobs;
+    l.nlr_max = e.nlr_max;
+    return launch_scan(l, s);
+}
+
+// One turn of every job: phasor scan (advances the clocks), push, prep of the
+// next turn.  With a timer, four events bracket the three parts.
+hipError_t enqueue_turn(const Engine &e, hipStream_t s, Timer *tm)
+{
+    hipEvent_t *ev = nullptr;
+    if (tm && tm->n[0] < Timer::kMax)
+        ev = &tm->ev[0][4 * tm->n[0]++];
+    hipError_t r;
+    if (ev && (r = hipEventRecord(ev[0], s)) != hipSuccess)
+        return r;
+    if ((r = enqueue_scan(e, s)) != hipSuccess)
+        return r;
+    if (ev && (r = hipEventRecord(ev[1], s)) != hipSuccess)
+        return r;
+    if ((r = enqueue_push(e, true, s)) != hipSuccess)
+        return r;
+    if (ev && (r = hipEventRecord(ev[2], s)) != hipSuccess)
+        return r;
+    if ((r = enqueue_prep(e, s)) != hipSuccess)
+        return r;
+    if (ev && (r = hipEventRecord(ev[3], s)) != hipSuccess)
+        return r;
+    return hipSuccess;
+}
+
+// Engine of one job, from the tables in its own workspace.
+Engine single_engine(const mbt_ctx *c)
+{
+    Engine e;
+    e.jobs = c->w<JobDesc>(c->L.desc);
+    e.push_items = c->w<Item>(c->L.items_push);
+    e.prep_items = c->w<Item>(c->L.items_prep);
+    e.njobs = 1;
+    e.nprep = c->M * c->L.nchunks;
+    e.nlr_max = c->nlr();
+    e.nbins_max = c->nbins();
+    Group g;
+    g.nitems = c->M * c->L.ntiles;
+    g.nlr = c->nlr();
+    g.nbins_max = c->nbins();
+    g.nsub_max = c->nsub;
+    g.grid = c->push_grid;
+    e.groups.push_back(g);
+    return e;
+}
+
+// Start of a call on job c, enqueued on stream s: upload its descriptor
+// (rings count from the present turn), and if the tile sums, histogram and
+// wake potential are stale, set the device clock and rebuild them with a
+// bin-only pass and a prep.
+int begin_call(mbt_ctx *c, int prof_stride, hipStream_t s)
+{
+    c->mirror->desc = job_desc(c, (uint32_t)c->turn, prof_stride);
+    HIPCHK(c, hipMemcpyAsync(c->w<JobDesc>(c->L.desc), &c->mirror->desc, sizeof(JobDesc),
+                             hipMemcpyHostToDevice, s));
     if (!c->dirty)
         return MBT_OK;
+    c->mirror->clock = (uint32_t)(c->turn - 1);
+    HIPCHK(c, hipMemcpyAsync(c->w<uint32_t>(c->L.clock), &c->mirror->clock, sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s));
     const int nbx = std::max(c->nbins(), 1);
     uint32_t *cnt = c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * nbx;
-    HIPCHK(c, hipMemsetAsync(cnt, 0, (size_t)c->M * nbx * sizeof(uint32_t), c->stream_h));
-    HIPCHK(c, launch_push(push_args(c, false), c->nlr(), false, c->stream_h));
+    HIPCHK(c, hipMemsetAsync(cnt, 0, (size_t)c->M * nbx * sizeof(uint32_t), s));
+    const Engine e = single_engine(c);
+    HIPCHK(c, enqueue_push(e, false, s));
+    HIPCHK(c, enqueue_prep(e, s));
     c->dirty = false;
     return MBT_OK;
 }
 
-int wait_pending(mbt_ctx *c, Pending &p, const void *src)
+// --- output rings --------------------------------------------------------
+
+int ring_alloc(mbt_ctx *c, RingOut &r, const void *dev, size_t row_bytes, int slots)
 {
-    if (!p.busy)
-        return MBT_OK;
-    HIPCHK(c, hipEventSynchronize(p.ev));
-    std::memcpy(p.dst, src, p.bytes);
-    p.busy = false;
+    r.dev = reinterpret_cast<const unsigned char *>(dev);
+    r.row_bytes = row_bytes;
+    r.slots = slots;
+    HIPCHK(c, hipHostMalloc((void **)&r.pin, (size_t)slots * row_bytes, hipHostMallocDefault));
+    HIPCHK(c, hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
     return MBT_OK;
 }
 
-// Copy `bytes` of a device ring to `dst` through pinned buffer `slot`.
-int stage_out(mbt_ctx *c, int slot, bool prof, const void *dev, void *dst, size_t bytes)
+void ring_free(RingOut &r)
 {
-    Pending &p = prof ? c->pend_prof[slot] : c->pend_mom[slot];
-    void *pin = prof ? c->pin_prof[slot] : c->pin_mom[slot];
-    int rc = wait_pending(c, p, pin);
-    if (rc)
-        return rc;
-    HIPCHK(c, hipMemcpyAsync(pin, dev, bytes, hipMemcpyDeviceToHost, c->stream_h));
-    HIPCHK(c, hipEventRecord(p.ev, c->stream_h));
-    p.dst = dst;
-    p.bytes = bytes;
-    p.busy = true;
-    return MBT_OK;
+    if (r.pin)
+        (void)hipHostFree(r.pin);
+    if (r.ev)
+        (void)hipEventDestroy(r.ev);
+    r = RingOut{};
 }
 
-int drain(mbt_ctx *c)
+void ring_start(RingOut &r, void *dst)
 {
-    for (int i = 0; i < 2; ++i) {
-        int rc = wait_pending(c, c->pend_mom[i], c->pin_mom[i]);
-        if (rc)
-            return rc;
-        rc = wait_pending(c, c->pend_prof[i], c->pin_prof[i]);
-        if (rc)
-            return rc;
+    r.dst = reinterpret_cast<unsigned char *>(dst);
+    r.flushed = r.written = 0;
+    r.pending.clear();
+}
+
+// Wait for the last copy out of the ring and move it to the host array.
+hipError_t ring_land(RingOut &r)
+{
+    if (r.pending.empty())
+        return hipSuccess;
+    hipError_t e = hipEventSynchronize(r.ev);
+    if (e != hipSuccess)
+        return e;
+    for (const RingOut::Piece &p : r.pending)
+        std::memcpy(r.dst + (size_t)p.row * r.row_bytes, r.pin + p.pin_off,
+                    (size_t)p.rows * r.row_bytes);
+    r.pending.clear();
+    return hipSuccess;
+}
+
+// Enqueue the copy of rows [flushed, written) (at most two contiguous runs
+// of slots) into the pinned buffer.
+hipError_t ring_flush(RingOut &r, hipStream_t s)
+{
+    if (!r.dst || r.written == r.flushed)
+        return hipSuccess;
+    hipError_t e = ring_land(r);
+    if (e != hipSuccess)
+        return e;
+    int64_t row = r.flushed;
+    while (row < r.written) {
+        const int64_t slot = row & (r.slots - 1);
+        const int64_t n = std::min<int64_t>(r.written - row, r.slots - slot);
+        const size_t off = (size_t)slot * r.row_bytes;
+        e = hipMemcpyAsync(r.pin + off, r.dev + off, (size_t)n * r.row_bytes,
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess)
+            return e;
+        r.pending.push_back({off, row, n});
+        row += n;
     }
-    return MBT_OK;
+    r.flushed = r.written;
+    return hipEventRecord(r.ev, s);
 }
 
-constexpr int kMaxTimed = 4096;
-
-void destroy_timing_events(mbt_ctx *c)
+// Make room for n more rows (n <= slots), then count them as written.
+hipError_t ring_advance(RingOut &r, int64_t n, hipStream_t s)
 {
-    for (hipEvent_t e : c->ev_push)
+    if (!r.dst || n == 0)
+        return hipSuccess;
+    if (r.written + n - r.flushed > r.slots) {
+        hipError_t e = ring_flush(r, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    r.written += n;
+    return hipSuccess;
+}
+
+// Profile rows among the turns [t0, t0 + n) of a call with this stride.
+int64_t profile_rows(int64_t t0, int64_t n, int stride)
+{
+    if (stride < 1)
+        return 0;
+    auto ceil_div = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+    return ceil_div(t0 + n, stride) - ceil_div(t0, stride);
+}
+
+// --- timing --------------------------------------------------------------
+
+void timer_free(Timer &t)
+{
+    for (hipEvent_t e : t.ev[0])
         (void)hipEventDestroy(e);
-    for (hipEvent_t e : c->ev_prep)
-        (void)hipEventDestroy(e);
-    c->ev_push.clear();
-    c->ev_prep.clear();
+    t.ev[0].clear();
 }
 
-// Launch helpers that bracket a launch with a timing event pair when asked.
-int timed_push(mbt_ctx *c, bool timed)
+hipError_t timer_set(Timer &t, int every)
 {
-    const bool t = timed && c->n_push_ev < kMaxTimed;
-    if (t)
-        HIPCHK(c, hipEventRecord(c->ev_push[2 * c->n_push_ev], c->stream_h));
-    HIPCHK(c, launch_push(push_args(c, true), c->nlr(), true, c->stream_h));
-    if (t)
-        HIPCHK(c, hipEventRecord(c->ev_push[2 * c->n_push_ev++ + 1], c->stream_h));
-    return MBT_OK;
-}
-
-int timed_prep(mbt_ctx *c, bool timed, double *slot)
-{
-    const bool t = timed && c->n_prep_ev < kMaxTimed;
-    if (t)
-        HIPCHK(c, hipEventRecord(c->ev_prep[2 * c->n_prep_ev], c->stream_h));
-    HIPCHK(c, launch_prep(prep_args(c, true, true, slot), c->stream_h));
-    if (t)
-        HIPCHK(c, hipEventRecord(c->ev_prep[2 * c->n_prep_ev++ + 1], c->stream_h));
-    return MBT_OK;
-}
-
-// After the stream has drained: add the recorded pairs to the totals.
-int collect_timing(mbt_ctx *c)
-{
-    for (int i = 0; i < c->n_push_ev; ++i) {
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_push[2 * i], c->ev_push[2 * i + 1]));
-        c->push_ms += ms;
+    t.every = every;
+    t.ms[0] = t.ms[1] = 0.0;
+    t.launches[0] = t.launches[1] = 0;
+    t.n[0] = 0;
+    if (every > 0 && t.ev[0].empty()) {
+        t.ev[0].resize(4 * Timer::kMax);
+        for (hipEvent_t &e : t.ev[0]) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess)
+                return r;
+        }
     }
-    for (int i = 0; i < c->n_prep_ev; ++i) {
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_prep[2 * i], c->ev_prep[2 * i + 1]));
-        c->prep_ms += ms;
+    return hipSuccess;
+}
+
+// After the stream has drained: add the recorded turns to the totals.
+hipError_t timer_collect(Timer &t)
+{
+    for (int i = 0; i < t.n[0]; ++i) {
+        const hipEvent_t *ev = &t.ev[0][4 * i];
+        float a = 0.f, b = 0.f, p = 0.f;
+        hipError_t r;
+        if ((r = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess ||
+            (r = hipEventElapsedTime(&p, ev[1], ev[2])) != hipSuccess ||
+            (r = hipEventElapsedTime(&b, ev[2], ev[3])) != hipSuccess)
+            return r;
+        t.ms[0] += p;
+        t.ms[1] += a + b;
     }
-    c->push_launches += c->n_push_ev;
-    c->prep_launches += c->n_prep_ev;
-    c->n_push_ev = c->n_prep_ev = 0;
-    return MBT_OK;
+    t.launches[0] += t.n[0];
+    t.launches[1] += t.n[0];
+    t.n[0] = 0;
+    return hipSuccess;
 }
 
 void release_binding(mbt_ctx *c)
 {
     if (c->bound)
         (void)hipStreamSynchronize(c->stream_h);
-    for (int i = 0; i < 2; ++i) {
-        if (c->pin_mom[i])
-            (void)hipHostFree(c->pin_mom[i]);
-        if (c->pin_prof[i])
-            (void)hipHostFree(c->pin_prof[i]);
-        c->pin_mom[i] = c->pin_prof[i] = nullptr;
-        if (c->pend_mom[i].ev)
-            (void)hipEventDestroy(c->pend_mom[i].ev);
-        if (c->pend_prof[i].ev)
-            (void)hipEventDestroy(c->pend_prof[i].ev);
-        c->pend_mom[i] = Pending{};
-        c->pend_prof[i] = Pending{};
-    }
+    ring_free(c->mom);
+    ring_free(c->prof);
+    if (c->mirror)
+        (void)hipHostFree(c->mirror);
+    c->mirror = nullptr;
     c->bound = false;
 }
 
@@ -458,7 +666,7 @@ void mbt_destroy(mbt_ctx *ctx)
     if (!ctx)
         return;
     release_binding(ctx);
-    destroy_timing_events(ctx);
+    timer_free(ctx->timer);
     delete ctx;
 }
 
@@ -651,6 +859,11 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
             qc[ix + 1] = qpp[b] * ci;
         }
     }
+    std::vector<Item> pitems, citems;
+    pitems.reserve((size_t)M * L.ntiles);
+    citems.reserve((size_t)M * L.nchunks);
+    push_items(c, 0, pitems);
+    prep_items(c, 0, citems);
     HIPCHK(c, hipMemsetAsync(c->work, 0, L.total, c->stream_h));
     HIPCHK(c, hipMemcpyAsync(c->w<double>(L.W), W.data(), W.size() * sizeof(double),
                              hipMemcpyHostToDevice, c->stream_h));
@@ -662,16 +875,25 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
                              hipMemcpyHostToDevice, c->stream_h));
     HIPCHK(c, hipMemcpyAsync(c->w<uint32_t>(L.stream), strm.data(), strm.size() * sizeof(uint32_t),
                              hipMemcpyHostToDevice, c->stream_h));
+    HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_push), pitems.data(), pitems.size() * sizeof(Item),
+                             hipMemcpyHostToDevice, c->stream_h));
+    HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_prep), citems.data(), citems.size() * sizeof(Item),
+                             hipMemcpyHostToDevice, c->stream_h));
     HIPCHK(c, hipMemsetAsync(d_state, 0, L.state_bytes, c->stream_h));
     HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    const size_t mom_bytes = (size_t)L.ring_turns * M * 4 * sizeof(double);
-    const size_t prof_bytes = (size_t)L.prof_slots * M * nbx * sizeof(uint32_t);
-    for (int i = 0; i < 2; ++i) {
-        HIPCHK(c, hipHostMalloc(&c->pin_mom[i], mom_bytes, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc(&c->pin_prof[i], prof_bytes, hipHostMallocDefault));
-        HIPCHK(c, hipEventCreateWithFlags(&c->pend_mom[i].ev, hipEventDisableTiming));
-        HIPCHK(c, hipEventCreateWithFlags(&c->pend_prof[i].ev, hipEventDisableTiming));
+    HIPCHK(c, hipHostMalloc((void **)&c->mirror, sizeof(Mirror), hipHostMallocDefault));
+    int rc = ring_alloc(c, c->mom, c->w<double>(L.mom), (size_t)M * sizeof(mbt_moments), L.mom_slots);
+    if (!rc)
+        rc = ring_alloc(c, c->prof, c->w<uint32_t>(L.prof), (size_t)M * nbx * sizeof(uint32_t),
+                        L.prof_slots);
+    if (rc) {
+        release_binding(c);
+        return rc;
     }
+    if (c->nsub == 0 || push_lds_bytes(nb, c->nsub) > kLdsLimit)
+        c->nsub = default_nsub(nb);
+    if (nb == 0)
+        c->nsub = 0;
     c->bound = true;
     c->have_particles = false;
     c->dirty = true;
@@ -741,81 +963,32 @@ int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, in
         return rc;
     if (!c->have_particles)
         return fail(c, MBT_ESTATE, "particles not initialised");
-    if (nturns < 0 || c->turn + nturns > ((int64_t)1 << 32))
-        return fail(c, MBT_EINVAL, "turn counter would pass 2^32");
+    if (nturns < 0 || nturns > INT32_MAX || c->turn + nturns > ((int64_t)1 << 32))
+        return fail(c, MBT_EINVAL, "need nturns < 2^31 and the turn counter below 2^32");
     if (counts && (!c->sr_on || stride < 1))
         return fail(c, MBT_EINVAL, "profiles need a grid and stride >= 1");
     if (nturns == 0)
         return MBT_OK;
-    rc = prologue(c);
+    hipStream_t s = c->stream_h;
+    rc = begin_call(c, counts ? stride : 0, s);
     if (rc)
         return rc;
-    const int M = c->M, nbx = std::max(c->nbins(), 1);
-    const int K = c->L.ring_turns, P = c->L.prof_slots;
-    const size_t mom_row = (size_t)M * 4 * sizeof(double);
-    const size_t prof_row = (size_t)M * nbx * sizeof(uint32_t);
-    double *ring = c->w<double>(c->L.mom);
-    uint32_t *pring = c->w<uint32_t>(c->L.prof);
-    int mom_chunk = 0, prof_chunk = 0;
-    int64_t mom_from = 0;   // first turn of the moment chunk being filled
-    int64_t prof_from = 0;  // first profile row of the chunk being filled
-    int64_t prof_rows = 0;
-
+    ring_start(c->mom, out);
+    ring_start(c->prof, counts);
+    const Engine e = single_engine(c);
     for (int64_t t = 0; t < nturns; ++t) {
-        const bool timed = c->timing_every > 0 && (t % c->timing_every) == 0;
-        // prep(n): moments of the state after turn t-1 of this call
-        double *slot = (out && t > 0) ? ring + (size_t)((t - 1) % K) * M * 4 : nullptr;
-        rc = timed_prep(c, timed, slot);
-        if (rc)
-            return rc;
-        if (out && t > 0 && (t - 1) % K == K - 1) {
-            rc = stage_out(c, mom_chunk & 1, false, ring, out + (size_t)mom_from * M,
-                           (size_t)K * mom_row);
-            if (rc)
-                return rc;
-            ++mom_chunk;
-            mom_from = t;
-        }
-        rc = timed_push(c, timed);
-        if (rc)
-            return rc;
-        c->turn += 1;
-        if (counts && t % stride == 0) {
-            const uint32_t *src = c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * M * nbx;
-            const int64_t row = t / stride;
-            HIPCHK(c, hipMemcpyAsync(pring + (size_t)(row % P) * M * nbx, src, prof_row,
-                                     hipMemcpyDeviceToDevice, c->stream_h));
-            ++prof_rows;
-            if (row % P == P - 1) {
-                rc = stage_out(c, prof_chunk & 1, true, pring,
-                               counts + (size_t)prof_from * M * nbx, (size_t)P * prof_row);
-                if (rc)
-                    return rc;
-                ++prof_chunk;
-                prof_from = row + 1;
-            }
-        }
+        const bool timed = c->timer.every > 0 && (t % c->timer.every) == 0;
+        HIPCHK(c, ring_advance(c->mom, 1, s));
+        HIPCHK(c, ring_advance(c->prof, profile_rows(t, 1, stride), s));
+        HIPCHK(c, enqueue_turn(e, s, timed ? &c->timer : nullptr));
     }
-    // Moments of the final state.
-    double *slot = out ? ring + (size_t)((nturns - 1) % K) * M * 4 : nullptr;
-    HIPCHK(c, launch_prep(prep_args(c, false, false, slot), c->stream_h));
-    if (out && nturns > mom_from)
-        rc = stage_out(c, mom_chunk & 1, false, ring, out + (size_t)mom_from * M,
-                       (size_t)(nturns - mom_from) * mom_row);
-    if (rc)
-        return rc;
-    if (counts && prof_rows > prof_from)
-        rc = stage_out(c, prof_chunk & 1, true, pring, counts + (size_t)prof_from * M * nbx,
-                       (size_t)(prof_rows - prof_from) * prof_row);
-    if (rc)
-        return rc;
-    HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    rc = drain(c);
-    if (rc)
-        return rc;
-    rc = collect_timing(c);
-    if (rc)
-        return rc;
+    c->turn += nturns;
+    HIPCHK(c, ring_flush(c->mom, s));
+    HIPCHK(c, ring_flush(c->prof, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, ring_land(c->mom));
+    HIPCHK(c, ring_land(c->prof));
+    HIPCHK(c, timer_collect(c->timer));
     uint32_t status = 0;
     HIPCHK(c, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
     if (status) {
@@ -835,9 +1008,10 @@ int mbt_profile(mbt_ctx *c, uint32_t *counts)
         return fail(c, MBT_EINVAL, "need a grid and an output array");
     if (!c->have_particles)
         return fail(c, MBT_ESTATE, "particles not initialised");
-    rc = prologue(c);
+    rc = begin_call(c, 0, c->stream_h);
     if (rc)
         return rc;
+    // the prep leaves the present state's histogram in counts[turn & 1]
     const size_t bytes = (size_t)c->M * c->nbins() * sizeof(uint32_t);
     HIPCHK(c, hipMemcpyAsync(counts, c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * c->nbins(),
                              bytes, hipMemcpyDeviceToHost, c->stream_h));
@@ -854,10 +1028,9 @@ int mbt_wake_potential(mbt_ctx *c, double *V)
         return fail(c, MBT_EINVAL, "need a grid and an output array");
     if (!c->have_particles)
         return fail(c, MBT_ESTATE, "particles not initialised");
-    rc = prologue(c);
+    rc = begin_call(c, 0, c->stream_h);
     if (rc)
         return rc;
-    HIPCHK(c, launch_prep(prep_args(c, true, false, nullptr), c->stream_h));
     HIPCHK(c, hipMemcpyAsync(V, c->w<double>(c->L.V), (size_t)c->M * c->nbins() * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream_h));
     HIPCHK(c, hipStreamSynchronize(c->stream_h));
@@ -920,18 +1093,7 @@ int mbt_set_timing(mbt_ctx *c, int32_t every)
 {
     if (!c || every < 0)
         return MBT_EINVAL;
-    c->timing_every = every;
-    c->push_ms = c->prep_ms = 0.0;
-    c->push_launches = c->prep_launches = 0;
-    c->n_push_ev = c->n_prep_ev = 0;
-    if (every > 0 && c->ev_push.empty()) {
-        c->ev_push.resize(2 * kMaxTimed);
-        c->ev_prep.resize(2 * kMaxTimed);
-        for (hipEvent_t &e : c->ev_push)
-            HIPCHK(c, hipEventCreate(&e));
-        for (hipEvent_t &e : c->ev_prep)
-            HIPCHK(c, hipEventCreate(&e));
-    }
+    HIPCHK(c, timer_set(c->timer, every));
     return MBT_OK;
 }
 
@@ -941,13 +1103,26 @@ int mbt_get_timing(const mbt_ctx *c, double *push_ms, int64_t *push_launches, do
     if (!c)
         return MBT_EINVAL;
     if (push_ms)
-        *push_ms = c->push_ms;
+        *push_ms = c->timer.ms[0];
     if (push_launches)
-        *push_launches = c->push_launches;
+        *push_launches = c->timer.launches[0];
     if (prep_ms)
-        *prep_ms = c->prep_ms;
+        *prep_ms = c->timer.ms[1];
     if (prep_launches)
-        *prep_launches = c->prep_launches;
+        *prep_launches = c->timer.launches[1];
+    return MBT_OK;
+}
+
+int mbt_set_launch(mbt_ctx *c, int32_t nsub, int32_t push_grid)
+{
+    if (!c)
+        return MBT_EINVAL;
+    const int nb = c->nbins();
+    if (push_grid < 0 || nsub < 0 || (nb > 0 && nsub > 0 && push_lds_bytes(nb, nsub) > kLdsLimit))
+        return fail(c, MBT_EINVAL, "need push_grid >= 0 and 0 <= nsub with the LDS image <= %zu bytes",
+                    kLdsLimit);
+    c->nsub = nb == 0 ? 0 : (nsub == 0 ? default_nsub(nb) : nsub);
+    c->push_grid = push_grid;
     return MBT_OK;
 }
 
@@ -958,6 +1133,491 @@ int mbt_philox4x32_10(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t ke
         return MBT_EINVAL;
     if (launch_philox(n, ctr, key0, key1, out, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
         return MBT_EDEVICE;
+    return MBT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: several bound jobs advanced together, every kernel launch
+// covering all bunches of all jobs.  Optionally a run of turns is captured
+// once as a HIP graph and replayed; optionally the launch shape of the push
+// is tuned online on the first turns.
+// ---------------------------------------------------------------------------
+
+struct mbt_batch {
+    std::vector<mbt_ctx *> jobs;
+    unsigned char *work = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;   // private stream that graphs are captured on
+    JobDesc *pin_desc = nullptr; // pinned [njobs]
+    size_t off_push = 0, off_prep = 0, total = 0;
+    Engine eng;
+    int graph_turns = 0;
+    bool autotune = false, tuned = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int exec_turns = 0;
+    char err[512] = "";
+};
+
+namespace {
+
+size_t batch_layout(mbt_ctx *const *jobs, int n, size_t *off_push, size_t *off_prep)
+{
+    size_t np = 0, nc = 0;
+    for (int j = 0; j < n; ++j) {
+        np += (size_t)jobs[j]->M * jobs[j]->L.ntiles;
+        nc += (size_t)jobs[j]->M * jobs[j]->L.nchunks;
+    }
+    size_t o = align256((size_t)n * sizeof(JobDesc));
+    *off_push = o;
+    o = align256(o + np * sizeof(Item));
+    *off_prep = o;
+    o = align256(o + nc * sizeof(Item));
+    return o;
+}
+
+void drop_graph(mbt_batch *B)
+{
+    if (B->exec)
+        (void)hipGraphExecDestroy(B->exec);
+    if (B->graph)
+        (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->exec_turns = 0;
+}
+
+// Launch-shape choices found by the tuner, by (group nlr, largest nbins,
+// log2 of the item count).
+struct TuneKey {
+    int nlr, nbins, log_items;
+    bool operator<(const TuneKey &o) const
+    {
+        return nlr != o.nlr ? nlr < o.nlr : nbins != o.nbins ? nbins < o.nbins : log_items < o.log_items;
+    }
+};
+struct TuneChoice {
+    int nsub, grid;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune_cache;
+
+TuneKey tune_key(const Group &g)
+{
+    int l = 0;
+    while ((1 << (l + 1)) <= g.nitems && l < 30)
+        ++l;
+    return TuneKey{g.nlr, g.nbins_max, l};
+}
+
+// Set the sub-histogram count of every job of group gi (and the group's
+// LDS bound) and its push grid.
+void apply_choice(mbt_batch *B, int gi, TuneChoice ch)
+{
+    Group &g = B->eng.groups[gi];
+    g.grid = ch.grid;
+    g.nsub_max = 0;
+    for (mbt_ctx *c : B->jobs)
+        if (c->nlr() == g.nlr) {
+            c->nsub = c->nbins() > 0 ? ch.nsub : 0;
+            g.nsub_max = std::max(g.nsub_max, c->nsub);
+        }
+}
+
+// Upload every job's descriptor (after begin_call has refreshed its mirror).
+// The pinned image may still be read by an earlier copy: drain first.
+int upload_descs(mbt_batch *B)
+{
+    HIPCHK(B, hipStreamSynchronize(B->stream));
+    for (size_t j = 0; j < B->jobs.size(); ++j) {
+        mbt_ctx *c = B->jobs[j];
+        B->pin_desc[j] = c->mirror->desc;
+        B->pin_desc[j].nsub = c->nsub;
+    }
+    HIPCHK(B, hipMemcpyAsync(B->work, B->pin_desc, B->jobs.size() * sizeof(JobDesc),
+                             hipMemcpyHostToDevice, B->stream));
+    return MBT_OK;
+}
+
+// Rings of every job for turns [t, t + n) of the call.
+int batch_rings(mbt_batch *B, int64_t t, int64_t n, const int32_t *stride)
+{
+    for (size_t j = 0; j < B->jobs.size(); ++j) {
+        mbt_ctx *c = B->jobs[j];
+        HIPCHK(B, ring_advance(c->mom, n, B->stream));
+        if (stride)
+            HIPCHK(B, ring_advance(c->prof, profile_rows(t, n, stride[j]), B->stream));
+    }
+    return MBT_OK;
+}
+
+// Online tuning over real turns [t, t + budget): every candidate shape of
+// every group runs for two turns with events around the push; the fastest
+// (minimum over its turns) is kept and cached.  The shapes do not change any
+// result bit, so the turns count as ordinary tracking.  Returns the turns used.
+int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *stride, int *rc)
+{
+    *rc = MBT_OK;
+    std::vector<std::vector<TuneChoice>> cand(B->eng.groups.size());
+    size_t ncand = 1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (size_t gi = 0; gi < B->eng.groups.size(); ++gi) {
+            const Group &g = B->eng.groups[gi];
+            auto it = g_tune_cache.find(tune_key(g));
+            if (it != g_tune_cache.end()) {
+                cand[gi].push_back(it->second);
+                continue;
+            }
+            std::vector<int> subs;
+            if (g.nbins_max == 0)
+                subs.push_back(0);
+            else
+                for (int n = 1; n <= 8; n *= 2)
+                    if (push_lds_bytes(g.nbins_max, n) <= kLdsLimit)
+                        subs.push_back(n);
+            std::vector<int> grids = {0};
+            for (int w : {512, 1024, 2048})
+                if (w < g.nitems)
+                    grids.push_back(w);
+            for (int n : subs)
+                for (int w : grids)
+                    cand[gi].push_back({n, w});
+            ncand = std::max(ncand, cand[gi].size());
+        }
+    }
+    const int reps = 2;
+    if (ncand == 1) {  // all cached
+        for (size_t gi = 0; gi < cand.size(); ++gi)
+            apply_choice(B, (int)gi, cand[gi][0]);
+        B->tuned = true;
+        *rc = upload_descs(B);
+        return 0;
+    }
+    if ((int64_t)ncand * reps > budget)
+        return 0;  // too few turns in this call; tune on a later one
+    std::vector<std::vector<float>> best(cand.size());
+    for (size_t gi = 0; gi < cand.size(); ++gi)
+        best[gi].assign(cand[gi].size(), 1e30f);
+    std::vector<hipEvent_t> ev(2 * cand.size());
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            *rc = fail(B, MBT_EDEVICE, "hipEventCreate failed");
+            return 0;
+        }
+    int64_t used = 0;
+    for (size_t k = 0; k < ncand && !*rc; ++k) {
+        for (size_t gi = 0; gi < cand.size(); ++gi)
+            apply_choice(B, (int)gi, cand[gi][std::min(k, cand[gi].size() - 1)]);
+        if ((*rc = upload_descs(B)))
+            break;
+        for (int r = 0; r < reps && !*rc; ++r, ++used) {
+            if ((*rc = batch_rings(B, t + used, 1, stride)))
+                break;
+            hipError_t e = enqueue_scan(B->eng, B->stream);
+            for (size_t gi = 0; gi < cand.size() && e == hipSuccess; ++gi) {
+                e = hipEventRecord(ev[2 * gi], B->stream);
+                if (e == hipSuccess)
+                    e = launch_push(push_launch(B->eng, B->eng.groups[gi]), true, B->stream);
+                if (e == hipSuccess)
+                    e = hipEventRecord(ev[2 * gi + 1], B->stream);
+            }
+            if (e == hipSuccess)
+                e = enqueue_prep(B->eng, B->stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(B->stream);
+            for (size_t gi = 0; gi < cand.size() && e == hipSuccess; ++gi) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ev[2 * gi], ev[2 * gi + 1]);
+                const size_t kk = std::min(k, cand[gi].size() - 1);
+                best[gi][kk] = std::min(best[gi][kk], ms);
+            }
+            if (e != hipSuccess)
+                *rc = fail(B, MBT_EDEVICE, "tuning turn failed: %s", hipGetErrorString(e));
+        }
+    }
+    for (hipEvent_t e : ev)
+        (void)hipEventDestroy(e);
+    if (*rc)
+        return used;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (size_t gi = 0; gi < cand.size(); ++gi) {
+            const size_t k = std::min_element(best[gi].begin(), best[gi].end()) - best[gi].begin();
+            g_tune_cache[tune_key(B->eng.groups[gi])] = cand[gi][k];
+            apply_choice(B, (int)gi, cand[gi][k]);
+        }
+    }
+    B->tuned = true;
+    *rc = upload_descs(B);
+    return used;
+}
+
+// Capture `turns` turns of the batch as a graph (on the private stream).
+int batch_capture(mbt_batch *B, int turns)
+{
+    drop_graph(B);
+    HIPCHK(B, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < turns && e == hipSuccess; ++k)
+        e = enqueue_turn(B->eng, B->cap, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return fail(B, MBT_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    B->graph = g;
+    HIPCHK(B, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    B->exec_turns = turns;
+    return MBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbt_batch_query_bytes(mbt_ctx *const *jobs, int32_t njobs, size_t *work_bytes)
+{
+    if (!jobs || njobs < 1 || njobs > 65535 || !work_bytes)
+        return MBT_EINVAL;
+    for (int j = 0; j < njobs; ++j)
+        if (!jobs[j] || !jobs[j]->bound)
+            return MBT_ESTATE;
+    size_t a, b;
+    *work_bytes = batch_layout(jobs, njobs, &a, &b);
+    return MBT_OK;
+}
+
+int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t work_bytes,
+                     void *hip_stream, mbt_batch **out)
+{
+    if (!out)
+        return MBT_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    int rc = mbt_batch_query_bytes(jobs, njobs, &need);
+    if (rc)
+        return rc;
+    if (!d_work || ((uintptr_t)d_work & 255))
+        return MBT_EINVAL;
+    if (work_bytes < need)
+        return MBT_ENOSPC;
+    for (int j = 0; j < njobs; ++j) {
+        if (jobs[j]->device != jobs[0]->device)
+            return MBT_EINVAL;
+        for (int k = 0; k < j; ++k)
+            if (jobs[k] == jobs[j])
+                return MBT_EINVAL;
+    }
+    mbt_batch *B = new (std::nothrow) mbt_batch();
+    if (!B)
+        return MBT_ENOMEM;
+    B->jobs.assign(jobs, jobs + njobs);
+    B->work = reinterpret_cast<unsigned char *>(d_work);
+    B->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep);
+    // items grouped by long-range count, jobs in the order given
+    std::vector<Item> pitems, citems;
+    Engine &e = B->eng;
+    for (int nlr = 0; nlr <= kMaxLR; ++nlr) {
+        Group g;
+        g.item0 = (int)pitems.size();
+        g.nlr = nlr;
+        for (int j = 0; j < njobs; ++j) {
+            mbt_ctx *c = jobs[j];
+            if (c->nlr() != nlr)
+                continue;
+            push_items(c, j, pitems);
+            g.nbins_max = std::max(g.nbins_max, c->nbins());
+            g.nsub_max = std::max(g.nsub_max, c->nsub);
+        }
+        g.nitems = (int)pitems.size() - g.item0;
+        if (g.nitems > 0)
+            e.groups.push_back(g);
+    }
+    for (int j = 0; j < njobs; ++j) {
+        prep_items(jobs[j], j, citems);
+        e.nlr_max = std::max(e.nlr_max, jobs[j]->nlr());
+        e.nbins_max = std::max(e.nbins_max, jobs[j]->nbins());
+    }
+    if (pitems.size() > (size_t)INT32_MAX || citems.size() > (size_t)INT32_MAX) {
+        delete B;
+        return MBT_EINVAL;
+    }
+    e.jobs = reinterpret_cast<const JobDesc *>(B->work);
+    e.push_items = reinterpret_cast<const Item *>(B->work + B->off_push);
+    e.prep_items = reinterpret_cast<const Item *>(B->work + B->off_prep);
+    e.njobs = njobs;
+    e.nprep = (int)citems.size();
+    auto bail = [&](hipError_t r) {
+        std::snprintf(B->err, sizeof B->err, "batch setup failed: %s", hipGetErrorString(r));
+        mbt_batch_destroy(B);
+        return MBT_EDEVICE;
+    };
+    hipError_t r;
+    if ((r = hipHostMalloc((void **)&B->pin_desc, (size_t)njobs * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
+        return bail(r);
+    if ((r = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking)) != hipSuccess)
+        return bail(r);
+    if ((r = hipMemcpyAsync(B->work + B->off_push, pitems.data(), pitems.size() * sizeof(Item),
+                            hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
+        (r = hipMemcpyAsync(B->work + B->off_prep, citems.data(), citems.size() * sizeof(Item),
+                            hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
+        (r = hipStreamSynchronize(B->stream)) != hipSuccess)
+        return bail(r);
+    *out = B;
+    return MBT_OK;
+}
+
+void mbt_batch_destroy(mbt_batch *B)
+{
+    if (!B)
+        return;
+    (void)hipStreamSynchronize(B->stream);
+    drop_graph(B);
+    if (B->cap)
+        (void)hipStreamDestroy(B->cap);
+    if (B->pin_desc)
+        (void)hipHostFree(B->pin_desc);
+    delete B;
+}
+
+const char *mbt_batch_last_error(const mbt_batch *B) { return B ? B->err : "null batch"; }
+
+int mbt_batch_configure(mbt_batch *B, int32_t graph_turns, int32_t autotune)
+{
+    if (!B || graph_turns < 0 || graph_turns > 1024 || (autotune != 0 && autotune != 1))
+        return MBT_EINVAL;
+    if (graph_turns != B->graph_turns)
+        drop_graph(B);
+    B->graph_turns = graph_turns;
+    B->autotune = autotune == 1;
+    return MBT_OK;
+}
+
+int mbt_batch_launch_info(const mbt_batch *B, int32_t *ngroups, int32_t *nlr, int32_t *nsub,
+                          int32_t *grid)
+{
+    if (!B || !ngroups)
+        return MBT_EINVAL;
+    *ngroups = (int32_t)B->eng.groups.size();
+    for (size_t g = 0; g < B->eng.groups.size(); ++g) {
+        const Group &G = B->eng.groups[g];
+        if (nlr)
+            nlr[g] = G.nlr;
+        if (nsub)
+            nsub[g] = G.nsub_max;
+        if (grid)
+            grid[g] = G.grid > 0 ? std::min(G.grid, G.nitems) : G.nitems;
+    }
+    return MBT_OK;
+}
+
+int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
+                    uint32_t *const *counts, const int32_t *stride)
+{
+    if (!B)
+        return MBT_EINVAL;
+    const int nj = (int)B->jobs.size();
+    if (nturns < 0 || nturns > INT32_MAX)
+        return fail(B, MBT_EINVAL, "need 0 <= nturns < 2^31");
+    for (int j = 0; j < nj; ++j) {
+        mbt_ctx *c = B->jobs[j];
+        if (!c->bound || !c->have_particles)
+            return fail(B, MBT_ESTATE, "job %d: not bound or particles not initialised", j);
+        if (c->turn + nturns > ((int64_t)1 << 32))
+            return fail(B, MBT_EINVAL, "job %d: turn counter would pass 2^32", j);
+        if (counts && counts[j] && (!c->sr_on || !stride || stride[j] < 1))
+            return fail(B, MBT_EINVAL, "job %d: profiles need a grid and stride >= 1", j);
+    }
+    if (nturns == 0)
+        return MBT_OK;
+    // per-job strides (0: no profiles)
+    std::vector<int32_t> st(nj, 0);
+    for (int j = 0; j < nj; ++j)
+        st[j] = (counts && counts[j]) ? stride[j] : 0;
+    // earlier work on the jobs' own streams first
+    for (mbt_ctx *c : B->jobs)
+        if (c->stream_h != B->stream)
+            HIPCHK(B, hipStreamSynchronize(c->stream_h));
+    for (int j = 0; j < nj; ++j) {
+        mbt_ctx *c = B->jobs[j];
+        int rc = begin_call(c, st[j], B->stream);
+        if (rc)
+            return fail(B, rc, "job %d: %s", j, c->err);
+        ring_start(c->mom, out ? out[j] : nullptr);
+        ring_start(c->prof, st[j] ? counts[j] : nullptr);
+    }
+    // LDS bound of each push group from the jobs' present sub-histogram counts
+    for (Group &g : B->eng.groups) {
+        int ns = 0;
+        for (mbt_ctx *c : B->jobs)
+            if (c->nlr() == g.nlr)
+                ns = std::max(ns, c->nsub);
+        if (ns != g.nsub_max)
+            drop_graph(B);
+        g.nsub_max = ns;
+    }
+    int rc = upload_descs(B);
+    if (rc)
+        return rc;
+    int64_t t = 0;
+    if (B->autotune && !B->tuned) {
+        t = batch_tune(B, 0, nturns, st.data(), &rc);
+        if (rc)
+            return rc;
+        if (B->tuned)
+            drop_graph(B);
+    }
+    // turns per graph: whole rings' worth of rows at most
+    int G = B->graph_turns;
+    for (int j = 0; j < nj && G > 0; ++j) {
+        mbt_ctx *c = B->jobs[j];
+        G = std::min(G, c->L.mom_slots);
+        if (st[j])
+            G = (int)std::min<int64_t>(G, (int64_t)c->L.prof_slots * st[j]);
+    }
+    if (G > 1) {
+        if (B->exec_turns != G)
+            if ((rc = batch_capture(B, G)))
+                return rc;
+        for (; t + G <= nturns; t += G) {
+            if ((rc = batch_rings(B, t, G, st.data())))
+                return rc;
+            HIPCHK(B, hipGraphLaunch(B->exec, B->stream));
+        }
+    }
+    for (; t < nturns; ++t) {
+        if ((rc = batch_rings(B, t, 1, st.data())))
+            return rc;
+        HIPCHK(B, enqueue_turn(B->eng, B->stream, nullptr));
+    }
+    for (mbt_ctx *c : B->jobs) {
+        c->turn += nturns;
+        HIPCHK(B, ring_flush(c->mom, B->stream));
+        HIPCHK(B, ring_flush(c->prof, B->stream));
+    }
+    HIPCHK(B, hipStreamSynchronize(B->stream));
+    int bad = -1;
+    for (int j = 0; j < nj; ++j) {
+        mbt_ctx *c = B->jobs[j];
+        HIPCHK(B, ring_land(c->mom));
+        HIPCHK(B, ring_land(c->prof));
+        uint32_t status = 0;
+        HIPCHK(B, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
+        if (status) {
+            HIPCHK(B, hipMemset(c->w<uint32_t>(c->L.status), 0, sizeof status));
+            if (bad < 0)
+                bad = j;
+        }
+    }
+    if (bad >= 0)
+        return fail(B, MBT_ENUMERIC, "job %d: non-finite bunch moment", bad);
     return MBT_OK;
 }
 

@@ -1,5 +1,5 @@
-// mbt_internal.h -- parameter blocks shared by the host runtime and the HIP
-// kernels of the tracker (not part of the public ABI).
+// mbt_internal.h -- device-side job descriptors and kernel launchers of the
+// tracker (not part of the public ABI).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +19,7 @@ constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // particle pairs per thr
 constexpr int kTile = kPushThreads * 2 * kPairsPerThread;  // particles per tile
 constexpr int kPartStride = 4 + 2 * kMaxLR;  // doubles per tile partial
 constexpr int kPrepThreads = 256;
+constexpr int kConvOut = 64;         // wake-potential bins per workgroup
 constexpr int kRowAlign = 64;        // particle rows padded to 64 doubles (512 B)
 
 // Per-turn constants of the single-particle map and the binning grid.
@@ -44,58 +45,82 @@ struct MapConst {
     double lr_wbar[kMaxLR];   // sqrt(omega_r^2 - alpha^2)
 };
 
-// Push (and bin-only prologue) kernel arguments.
-struct PushArgs {
+// Everything a kernel needs about one job, resident in device memory.  The
+// turn counter `clock` holds the index of the last completed turn (turn - 1,
+// modulo 2^32); it is advanced on the device once per turn, so a captured
+// turn replays without parameter updates.
+struct JobDesc {
     MapConst c;
     double *tau;              // [M][ld]
     double *delta;            // [M][ld]
     int64_t ld;               // row stride in doubles
     int64_t N;                // particles per bunch
     int M;
-    int ntiles;               // tiles per bunch
-    int nsub;                 // LDS sub-histograms
-    const double *V;          // [M][nbins] wake potential (push only)
-    const double *seen;       // [nlr][M][2] long-range voltage seen by each bunch
-    const uint32_t *stream;   // [M] random-stream ordinals
-    uint32_t *counts_out;     // [M][nbins] histogram of the new tau (atomics)
-    double *partials;         // [M][ntiles][kPartStride]
+    int ntiles;               // push tiles per bunch
+    int nsub;                 // LDS sub-histograms in the push
+    int nlr;                  // long-range resonators
+    int mom_slots;            // moment ring rows (power of two)
+    int prof_stride;          // profile every prof_stride-th turn (0: off)
+    int prof_slots;           // profile ring rows (power of two)
+    uint32_t base;            // first turn of the present call: ring rows count from it
     uint32_t key0, key1;      // Philox key = seed
-    uint32_t turn;            // Philox counter word 2
-};
-
-// Between-turn kernel arguments: moments, wake potential, long-range scan.
-struct PrepArgs {
-    int M;
-    int ntiles;
-    int64_t N;
-    int nbins;
-    int nlr;
-    int do_conv;              // compute V from counts_in
-    int do_scan;              // advance the long-range phasors
-    const double *partials;   // [M][ntiles][kPartStride] from the last push/prologue
-    double *mom_out;          // [M][4] moments slot or nullptr
-    const uint32_t *counts_in;   // [M][nbins]
-    uint32_t *counts_clear;      // [M][nbins] zeroed for the next push
     const double *W;          // [nbins] wake table
-    const double *qpp;        // [M] charge per macro-particle I_b T0 / N
-    double *V;                // [M][nbins]
+    const double *qpp;        // [M] charge per macro-particle
     const double *gap;        // [nlr][M][2] rotation into bunch b's bucket
     const double *qc;         // [nlr][M][2] qpp_b * c_r
-    double *S;                // [nlr][M][2] deposit sums of each bunch
-    double *phasor;           // [nlr][2] state
-    double *seen;             // [nlr][M][2]
+    const uint32_t *stream;   // [M] random-stream ordinals
+    double *V;                // [M][nbins] wake potential
+    double *partials;         // [M][ntiles][kPartStride] tile sums
+    double *S;                // [nlr][M][2] deposit sums
+    double *seen;             // [nlr][M][2] voltage seen by each bunch
+    double *phasor;           // [nlr][2]
+    double *mom_ring;         // [mom_slots][M][4]
+    uint32_t *counts;         // [2][M][max(nbins,1)] histograms by turn parity
+    uint32_t *prof_ring;      // [prof_slots][M][nbins]
     uint32_t *status;         // bit 0: non-finite moment
+    uint32_t *clock;          // last completed turn (mod 2^32)
 };
 
-// Kernel launchers (mbt_kernels.hip).
-hipError_t launch_push(const PushArgs &a, int nlr, bool push, hipStream_t s);
-hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
+// One unit of work: a tile (push) or a wake-potential chunk (prep) of a bunch.
+struct Item {
+    uint16_t job;
+    uint16_t bunch;
+    uint32_t part;
+};
+
+// Launch descriptors.
+struct PushLaunch {
+    const JobDesc *jobs;
+    const Item *items;
+    int nitems;
+    int nlr;                  // template group: every job of the items has this many
+    int nbins_max;
+    int nsub_max;
+    int grid;                 // workgroups; each takes items g, g + grid, ...
+};
+struct PrepLaunch {
+    const JobDesc *jobs;
+    const Item *items;        // (job, bunch, chunk)
+    int nitems;
+    int nlr_max;
+    int nbins_max;
+    int do_conv;              // 0: moments only (the state at the end of a call)
+};
+struct ScanLaunch {
+    const JobDesc *jobs;
+    int njobs;
+    int nlr_max;
+};
+
+hipError_t launch_push(const PushLaunch &l, bool push, hipStream_t s);
+hipError_t launch_prep(const PrepLaunch &l, hipStream_t s);
+hipError_t launch_scan(const ScanLaunch &l, hipStream_t s);
 hipError_t launch_init_gauss(double *tau, double *delta, int64_t ld, int64_t N, int M,
                              const uint32_t *stream, double sig_tau, double sig_delta,
                              uint32_t key0, uint32_t key1, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1,
                          uint32_t *out, hipStream_t s);
 size_t push_lds_bytes(int nbins, int nsub);
-int push_nsub(int nbins);
+int conv_chunks(int nbins);
 
 }  // namespace mbt

@@ -1,16 +1,18 @@
 // mbt_kernels.hip -- HIP kernels of the longitudinal multi-bunch tracker for
 // CDNA4 (gfx950).
 //
-// One turn is two launches on the caller's stream (three with long-range
-// resonators):
-//   k_prep  (M x ceil(nbins/64) workgroups): finishes the previous push's
-//           per-bunch sums (moments, Sec. 2.4, and long-range deposits) and
-//           builds each bunch's binned wake potential from its line density
-//           (Sec. 2.3);
-//   k_scan  (one workgroup, with long-range resonators): advances the
-//           long-range phasors through the bunches in bucket order as a scan
-//           of affine maps.
-//   k_push  (tiles x M workgroups): the single-particle map of every particle
+// One turn is three launches on the caller's stream, each covering every
+// bunch of every job it is given (jobs are described by device-resident
+// descriptors, work by item lists, and each job's turn counter lives on the
+// device, so a turn can be captured once and replayed):
+//   k_prep  (per bunch, one workgroup per 64 bins): finishes the previous
+//           push's per-bunch sums (moments, Sec. 2.4, and long-range
+//           deposits) and builds each bunch's binned wake potential from its
+//           line density (Sec. 2.3);
+//   k_scan  (one workgroup per job): advances the job's turn counter and its
+//           long-range phasors through the bunches in bucket order (a scan
+//           of affine maps);
+//   k_push  (tiles of 4096 particles): the single-particle map of every particle
 //           (Sec. 2.2: Eq. 1 kick with RF, harmonic cavity and U0; Eq. 6
 //           short-range kick of the particle's bin; long-range kick; Eq. 5
 //           damping and quantum excitation; Eq. 2 drift), then -- on the new
@@ -192,31 +194,22 @@ size_t push_lds_bytes(int nbins, int nsub)
     return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
 }
 
-int push_nsub(int nbins)
-{
-    if (nbins <= 0)
-        return 0;
-    if (nbins <= 1024)
-        return 4;
-    if (nbins <= 2048)
-        return 2;
-    return 1;
-}
+int conv_chunks(int nbins) { return nbins > 0 ? (nbins + kConvOut - 1) / kConvOut : 1; }
 
 // Map and epilogue of the pair (t0, d0), (t1, d1) = particles 2p, 2p + 1
 // (the second only if `two`); the pushed coordinates are returned in place.
 template <int NLR, bool PUSH>
-__device__ __forceinline__ void pair_compute(const PushArgs &a, const double *Vs,
+__device__ __forceinline__ void pair_compute(const MapConst &c, uint32_t key0, uint32_t key1,
+                                             uint32_t turn, const double *Vs,
                                              const double (&seen)[NLR > 0 ? NLR : 1][2],
                                              uint32_t *hist_w, uint32_t p, uint32_t stream,
                                              bool two, double &t0, double &t1, double &d0,
                                              double &d1, double *acc)
 {
-    const MapConst &c = a.c;
     if (PUSH) {
         double z0 = 0.0, z1 = 0.0;
         if (c.noise_on)
-            normal_pair(p, stream, a.turn, 0u, a.key0, a.key1, z0, z1);
+            normal_pair(p, stream, turn, 0u, key0, key1, z0, z1);
         double s0, c0, s1, c1;
         rf_phase(c.w_rf * t0, c.w_rf * t1, s0, c0, s1, c1);
         kick_drift<NLR>(c, Vs, seen, s0, c0, z0, t0, d0);
@@ -227,169 +220,189 @@ __device__ __forceinline__ void pair_compute(const PushArgs &a, const double *Vs
         epilogue<NLR>(c, hist_w, t1, d1, acc);
 }
 
-// One pair with bounds handling (a bunch's last tile).
-template <int NLR, bool PUSH>
-__device__ __forceinline__ void pair_step(const PushArgs &a, const double *Vs,
-                                          const double (&seen)[NLR > 0 ? NLR : 1][2],
-                                          uint32_t *hist_w, double *tau, double *del, uint32_t p,
-                                          uint32_t stream, bool two, double *acc)
+// A wavefront-uniform copy of *p held in scalar registers: the descriptors
+// live in memory the kernels also write, so the compiler cannot prove them
+// unchanged and would otherwise keep every field in vector registers.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *p)
 {
-    const uint32_t j0 = 2u * p;
-    double t0, t1 = 0.0, d0, d1 = 0.0;
-    if (two) {
-        const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
-        const double2 dv = *reinterpret_cast<const double2 *>(del + j0);
-        t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
-    } else {
-        t0 = tau[j0];
-        d0 = del[j0];
-    }
-    pair_compute<NLR, PUSH>(a, Vs, seen, hist_w, p, stream, two, t0, t1, d0, d1, acc);
-    if (PUSH) {
-        if (two) {
-            *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
-            *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
-        } else {
-            tau[j0] = t0;
-            del[j0] = d0;
-        }
-    }
+    static_assert(sizeof(T) % 4 == 0, "word-sized descriptor");
+    T v;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
+        dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return v;
 }
 
 // ---------------------------------------------------------------------------
-// k_push: grid (ntiles, M), 256 threads.  PUSH = false is the bin-only
-// prologue that produces the histogram, deposits and moments of the present
-// state without moving it.  All tiles but a bunch's last are full and run a
-// loop without bounds checks.
+// k_push: each workgroup (256 threads) takes items g, g + grid, ... of the
+// item list; an item is one tile of 4096 particles of one bunch of one job.
+// PUSH = false is the bin-only prologue that produces the histogram,
+// deposits and moment sums of the present state without moving it.  Both
+// write the histogram into counts[(clock + 1) & 1]: during the push of turn
+// n the clock reads n, during the prologue at the start of turn n it reads
+// n - 1.  Full tiles run a loop without bounds checks that loads the next
+// pair before computing the current one.
 // ---------------------------------------------------------------------------
 template <int NLR, bool PUSH>
-__global__ __launch_bounds__(kPushThreads) void k_push(const PushArgs a)
+__global__ __launch_bounds__(kPushThreads) void k_push(const PushLaunch L)
 {
     extern __shared__ double smem[];
-    const MapConst &c = a.c;
-    const int nb = c.nbins;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int b = blockIdx.y;
-    const int tile = blockIdx.x;
-
-    double *Vs = smem;
-    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb);
-    double *red = smem + nb + ((a.nsub * nb + 1) >> 1);
-
-    for (int k = tid; k < a.nsub * nb; k += kPushThreads)
-        hist[k] = 0u;
-    if (PUSH && c.sr_on)
-        for (int k = tid; k < nb; k += kPushThreads)
-            Vs[k] = a.V[(size_t)b * nb + k] * c.inv_E0;
-    __syncthreads();
-    uint32_t *hist_w = hist + (a.nsub > 0 ? (wave % a.nsub) * nb : 0);
-
-    double seen[NLR > 0 ? NLR : 1][2];
-#pragma unroll
-    for (int r = 0; r < NLR; ++r) {
-        seen[r][0] = a.seen[((size_t)r * a.M + b) * 2 + 0] * c.inv_E0;
-        seen[r][1] = a.seen[((size_t)r * a.M + b) * 2 + 1] * c.inv_E0;
-    }
-    const uint32_t stream = a.stream[b];
-
-    double *tau = a.tau + (size_t)b * a.ld;
-    double *del = a.delta + (size_t)b * a.ld;
     constexpr int NP = 4 + 2 * NLR;
-    double acc[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-        acc[i] = 0.0;
 
-    // Indices within the bunch fit 32 bits (N <= 2^32, so a pair index < 2^31).
-    const uint32_t pair0 = (uint32_t)tile * (kPushThreads * kPairsPerThread);
-    if ((int64_t)(pair0 + kPushThreads * kPairsPerThread) * 2 <= a.N) {
-        // Full tile: the next pair's coordinates are loaded before the
-        // current pair is computed, so each wavefront keeps a load in flight.
-        uint32_t p = pair0 + (uint32_t)tid;
-        double2 tv = *reinterpret_cast<const double2 *>(tau + 2u * p);
-        double2 dv = *reinterpret_cast<const double2 *>(del + 2u * p);
-#pragma unroll 1
-        for (int it = 0; it < kPairsPerThread; ++it) {
-            double2 tn = tv, dn = dv;
-            if (it + 1 < kPairsPerThread) {
-                tn = *reinterpret_cast<const double2 *>(tau + 2u * (p + kPushThreads));
-                dn = *reinterpret_cast<const double2 *>(del + 2u * (p + kPushThreads));
-            }
-            double t0 = tv.x, t1 = tv.y, d0 = dv.x, d1 = dv.y;
-            pair_compute<NLR, PUSH>(a, Vs, seen, hist_w, p, stream, true, t0, t1, d0, d1, acc);
-            if (PUSH) {
-                *reinterpret_cast<double2 *>(tau + 2u * p) = make_double2(t0, t1);
-                *reinterpret_cast<double2 *>(del + 2u * p) = make_double2(d0, d1);
-            }
-            tv = tn;
-            dv = dn;
-            p += kPushThreads;
-        }
-    } else {
-        const uint32_t n_part = (uint32_t)(a.N - 1);  // last particle index
-#pragma unroll 1
-        for (int it = 0; it < kPairsPerThread; ++it) {
-            const uint32_t p = pair0 + (uint32_t)(it * kPushThreads + tid);
-            if (2u * p > n_part)
-                break;
-            pair_step<NLR, PUSH>(a, Vs, seen, hist_w, tau, del, p, stream, 2u * p < n_part, acc);
-        }
-    }
+    for (int it = blockIdx.x; it < L.nitems; it += L.grid) {
+        const Item item = load_uniform(L.items + it);
+        const JobDesc J = load_uniform(L.jobs + item.job);
+        const MapConst &c = J.c;
+        const int nb = c.nbins, nbx = nb > 0 ? nb : 1;
+        const int b = item.bunch;
+        const uint32_t tile = item.part;
+        const uint32_t clock = __builtin_amdgcn_readfirstlane(*J.clock);
+        const uint32_t turn = clock;  // push of turn n runs with the clock at n
 
-    // Fixed-order tile reduction: wave butterflies, then waves in order.
+        double *Vs = smem;
+        uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb);
+        double *red = smem + nb + ((J.nsub * nb + 1) >> 1);
+
+        for (int k = tid; k < J.nsub * nb; k += kPushThreads)
+            hist[k] = 0u;
+        if (PUSH && c.sr_on)
+            for (int k = tid; k < nb; k += kPushThreads)
+                Vs[k] = J.V[(size_t)b * nb + k] * c.inv_E0;
+        __syncthreads();
+        uint32_t *hist_w = hist + (J.nsub > 0 ? (wave % J.nsub) * nb : 0);
+
+        double seen[NLR > 0 ? NLR : 1][2];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const double v = wave_sum(acc[i]);
-        if (lane == 0)
-            red[wave * kPartStride + i] = v;
-    }
-    __syncthreads();
-    if (tid < NP) {
-        double s = red[tid];
-        for (int w = 1; w < kPushThreads / 64; ++w)
-            s += red[w * kPartStride + tid];
-        a.partials[((size_t)b * a.ntiles + tile) * kPartStride + tid] = s;
-    }
-    // Merge the LDS sub-histograms into the bunch's global histogram.
-    if (c.sr_on) {
-        for (int k = tid; k < nb; k += kPushThreads) {
-            uint32_t s = 0;
-            for (int q = 0; q < a.nsub; ++q)
-                s += hist[q * nb + k];
-            if (s)
-                atomicAdd(&a.counts_out[(size_t)b * nb + k], s);
+        for (int r = 0; r < NLR; ++r) {
+            seen[r][0] = J.seen[((size_t)r * J.M + b) * 2 + 0] * c.inv_E0;
+            seen[r][1] = J.seen[((size_t)r * J.M + b) * 2 + 1] * c.inv_E0;
         }
+        const uint32_t stream = J.stream[b];
+        double *tau = J.tau + (size_t)b * J.ld;
+        double *del = J.delta + (size_t)b * J.ld;
+        double acc[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            acc[i] = 0.0;
+
+        // Indices within the bunch fit 32 bits (N <= 2^32, a pair index < 2^31).
+        const uint32_t pair0 = tile * (uint32_t)(kPushThreads * kPairsPerThread);
+        if ((int64_t)(pair0 + kPushThreads * kPairsPerThread) * 2 <= J.N) {
+            uint32_t p = pair0 + (uint32_t)tid;
+            double2 tv = *reinterpret_cast<const double2 *>(tau + 2u * p);
+            double2 dv = *reinterpret_cast<const double2 *>(del + 2u * p);
+#pragma unroll 1
+            for (int s = 0; s < kPairsPerThread; ++s) {
+                double2 tn = tv, dn = dv;
+                if (s + 1 < kPairsPerThread) {
+                    tn = *reinterpret_cast<const double2 *>(tau + 2u * (p + kPushThreads));
+                    dn = *reinterpret_cast<const double2 *>(del + 2u * (p + kPushThreads));
+                }
+                double t0 = tv.x, t1 = tv.y, d0 = dv.x, d1 = dv.y;
+                pair_compute<NLR, PUSH>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, true,
+                                        t0, t1, d0, d1, acc);
+                if (PUSH) {
+                    *reinterpret_cast<double2 *>(tau + 2u * p) = make_double2(t0, t1);
+                    *reinterpret_cast<double2 *>(del + 2u * p) = make_double2(d0, d1);
+                }
+                tv = tn;
+                dv = dn;
+                p += kPushThreads;
+            }
+        } else {
+            const uint32_t n_last = (uint32_t)(J.N - 1);  // last particle index
+#pragma unroll 1
+            for (int s = 0; s < kPairsPerThread; ++s) {
+                const uint32_t p = pair0 + (uint32_t)(s * kPushThreads + tid);
+                const uint32_t j0 = 2u * p;
+                if (j0 > n_last)
+                    break;
+                const bool two = j0 < n_last;
+                double t0, t1 = 0.0, d0, d1 = 0.0;
+                if (two) {
+                    const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
+                    const double2 dv = *reinterpret_cast<const double2 *>(del + j0);
+                    t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
+                } else {
+                    t0 = tau[j0];
+                    d0 = del[j0];
+                }
+                pair_compute<NLR, PUSH>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, two,
+                                        t0, t1, d0, d1, acc);
+                if (PUSH) {
+                    if (two) {
+                        *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
+                        *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
+                    } else {
+                        tau[j0] = t0;
+                        del[j0] = d0;
+                    }
+                }
+            }
+        }
+
+        // Fixed-order tile reduction: wave butterflies, then waves in order.
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double v = wave_sum(acc[i]);
+            if (lane == 0)
+                red[wave * kPartStride + i] = v;
+        }
+        __syncthreads();
+        if (tid < NP) {
+            double sum = red[tid];
+            for (int w = 1; w < kPushThreads / 64; ++w)
+                sum += red[w * kPartStride + tid];
+            J.partials[((size_t)b * J.ntiles + tile) * kPartStride + tid] = sum;
+        }
+        // Merge the LDS sub-histograms into the bunch's histogram.
+        if (c.sr_on) {
+            uint32_t *out = J.counts + ((size_t)((clock + 1u) & 1u) * J.M + b) * nbx;
+            for (int k = tid; k < nb; k += kPushThreads) {
+                uint32_t sum = 0;
+                for (int q = 0; q < J.nsub; ++q)
+                    sum += hist[q * nb + k];
+                if (sum)
+                    atomicAdd(&out[k], sum);
+            }
+        }
+        __syncthreads();  // LDS is reused by the next item
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_prep: per bunch b, ceil(nbins/64) workgroups; the first of them also
-// finishes the bunch's moments.  Each workgroup builds 64 bins of the
-// bunch's wake potential, one wavefront per output bin with the lanes
-// splitting the sum over source bins.  One extra workgroup (when there are
-// long-range resonators) advances the phasors through the bunches in bucket
-// order.
+// k_prep: one workgroup per (job, bunch, 64-bin chunk).  With the clock at
+// n - 1 (start of turn n) it finishes the tile sums of the state after turn
+// n - 1 (moments into the ring row of that turn, deposit sums S), records
+// that state's histogram on profile turns, builds 64 bins of the wake
+// potential from it, and clears the histogram buffer the push of turn n
+// fills.
 // ---------------------------------------------------------------------------
-constexpr int kConvOut = 64;
 
 // Moments of bunch b from the tile sums of the last push (Sec. 2.4), and
 // the bunch's long-range deposit sums S[r][b] = sum_j exp((alpha - i wbar) tau_j).
 template <int NLR>
-__device__ void finish_sums(const PrepArgs &a, int b)
+__device__ void finish_sums(const JobDesc &J, int b, uint32_t clock)
 {
     constexpr int NP = 4 + 2 * NLR;
     __shared__ double sred[kPrepThreads / 64][NP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int np = 4 + 2 * J.nlr;
     double s[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i)
         s[i] = 0.0;
-    for (int t = tid; t < a.ntiles; t += kPrepThreads) {
-        const double *p = a.partials + ((size_t)b * a.ntiles + t) * kPartStride;
+    for (int t = tid; t < J.ntiles; t += kPrepThreads) {
+        const double *p = J.partials + ((size_t)b * J.ntiles + t) * kPartStride;
 #pragma unroll
         for (int i = 0; i < NP; ++i)
-            s[i] += p[i];
+            if (i < np)
+                s[i] += p[i];
     }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -405,35 +418,49 @@ __device__ void finish_sums(const PrepArgs &a, int b)
         sred[0][tid] = tot;
     }
     __syncthreads();
+    // turns since the start of the call; the state before its first turn
+    // (rel = -1) is neither stored nor recorded
+    const int32_t rel = (int32_t)(clock - J.base);
     if (tid == 0) {
-        const double invN = 1.0 / (double)a.N;
+        const double invN = 1.0 / (double)J.N;
         const double mt = sred[0][0] * invN, md = sred[0][2] * invN;
         const double vt = sred[0][1] * invN - mt * mt, vd = sred[0][3] * invN - md * md;
-        const double rms_t = sqrt(vt > 0.0 ? vt : 0.0), rms_d = sqrt(vd > 0.0 ? vd : 0.0);
-        if (a.mom_out) {
-            a.mom_out[4 * b + 0] = mt;
-            a.mom_out[4 * b + 1] = md;
-            a.mom_out[4 * b + 2] = rms_t;
-            a.mom_out[4 * b + 3] = rms_d;
+        if (rel >= 0) {
+            double *m = J.mom_ring + ((size_t)(rel & (J.mom_slots - 1)) * J.M + b) * 4;
+            m[0] = mt;
+            m[1] = md;
+            m[2] = sqrt(vt > 0.0 ? vt : 0.0);
+            m[3] = sqrt(vd > 0.0 ? vd : 0.0);
         }
         if (!isfinite(mt) || !isfinite(md) || !isfinite(vt) || !isfinite(vd))
-            atomicOr(a.status, 1u);
+            atomicOr(J.status, 1u);
     }
-    if (tid < 2 * NLR)
-        a.S[((size_t)(tid >> 1) * a.M + b) * 2 + (tid & 1)] = sred[0][4 + tid];
+    if (tid < 2 * J.nlr)
+        J.S[((size_t)(tid >> 1) * J.M + b) * 2 + (tid & 1)] = sred[0][4 + tid];
+    // histogram of this state on every prof_stride-th turn of the call
+    if (J.prof_stride > 0 && rel >= 0 && rel % J.prof_stride == 0) {
+        const int nb = J.c.nbins;
+        const uint32_t *src = J.counts + ((size_t)((clock + 1u) & 1u) * J.M + b) * nb;
+        const int row = (rel / J.prof_stride) & (J.prof_slots - 1);
+        uint32_t *dst = J.prof_ring + ((size_t)row * J.M + b) * nb;
+        for (int k = tid; k < nb; k += kPrepThreads)
+            dst[k] = src[k];
+    }
 }
 
 // Bins [k0, k1) of bunch b's wake potential (Sec. 2.3):
 // V[k] = qpp * sum_{m<=k} W[k-m] c[m].  Four threads per output bin, each
 // summing every fourth source bin with two accumulators; the four partial
 // sums are added in a fixed order.
-__device__ void conv_chunk(const PrepArgs &a, int b, int chunk, double *psm)
+__device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, double *psm)
 {
     __shared__ int s_lo;
     __shared__ double part[4][kConvOut];
     const int tid = threadIdx.x;
-    const int nb = a.nbins;
+    const int nb = J.c.nbins;
     const int k0 = chunk * kConvOut, k1 = min(k0 + kConvOut, nb);
+    const uint32_t *cin = J.counts + ((size_t)((clock + 1u) & 1u) * J.M + b) * nb;
+    uint32_t *cclr = J.counts + ((size_t)(clock & 1u) * J.M + b) * nb;
     double *sW = psm;        // W[0 .. k1)
     double *sc = psm + nb;   // c[0 .. k1)
     if (tid == 0)
@@ -441,8 +468,8 @@ __device__ void conv_chunk(const PrepArgs &a, int b, int chunk, double *psm)
     __syncthreads();
     int lo = k1;             // first occupied bin: nothing below it contributes
     for (int k = tid; k < k1; k += kPrepThreads) {
-        sW[k] = a.W[k];
-        const uint32_t cnt = a.counts_in[(size_t)b * nb + k];
+        sW[k] = J.W[k];
+        const uint32_t cnt = cin[k];
         sc[k] = (double)cnt;
         if (cnt && k < lo)
             lo = k;
@@ -466,19 +493,35 @@ __device__ void conv_chunk(const PrepArgs &a, int b, int chunk, double *psm)
     part[q][o] = acc0 + acc1;
     __syncthreads();
     if (tid < kConvOut && k < k1)
-        a.V[(size_t)b * nb + k] = a.qpp[b] * (((part[0][o] + part[1][o]) + part[2][o]) + part[3][o]);
+        J.V[(size_t)b * nb + k] = J.qpp[b] * (((part[0][o] + part[1][o]) + part[2][o]) + part[3][o]);
     for (int kk = k0 + tid; kk < k1; kk += kPrepThreads)
-        a.counts_clear[(size_t)b * nb + kk] = 0u;
+        cclr[kk] = 0u;
 }
 
-// Long-range phasors advanced bunch by bunch in bucket order.  Passing
-// bunch b maps the phasor x to G_b x + D_b (rotation across the gap from the
-// previous filled bucket, then the bunch's deposit D_b = qpp_b c_r S_b with
-// S_b = sum_j exp((alpha - i wbar) tau_j)), and the bunch sees G_b x.  The
-// chain of M affine maps is evaluated as a scan: each thread composes a
-// contiguous run of bunches, a Hillis-Steele scan over the 256 composed maps
-// (fixed order, so deterministic) gives each run its incoming phasor, and
-// each thread then replays its run to record what every bunch sees.
+template <int NLR>
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
+{
+    extern __shared__ double psm[];
+    const Item item = L.items[blockIdx.x];
+    const JobDesc &J = L.jobs[item.job];
+    const uint32_t clock = *J.clock;
+    if (item.part == 0)
+        finish_sums<NLR>(J, item.bunch, clock);
+    if (L.do_conv && J.c.sr_on)
+        conv_chunk(J, item.bunch, (int)item.part, clock, psm);
+}
+
+// ---------------------------------------------------------------------------
+// k_scan: one workgroup per job.  Advances the job's clock to the turn about
+// to be pushed, then carries its long-range phasors through the bunches in
+// bucket order.  Passing bunch b maps the phasor x to G_b x + D_b (rotation
+// across the gap from the previous filled bucket, then the bunch's deposit
+// D_b = qpp_b c_r S_b); the bunch sees G_b x.  The chain of M affine maps is
+// evaluated as a scan: each thread composes a contiguous run of bunches, a
+// Hillis-Steele scan over the 256 composed maps (fixed order, so
+// deterministic) gives each run its incoming phasor, and each thread then
+// replays its run to record what every bunch sees.
+// ---------------------------------------------------------------------------
 struct cplx {
     double re, im;
 };
@@ -491,20 +534,22 @@ __device__ __forceinline__ cplx cmuladd(cplx a, cplx b, cplx c)
     return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
 }
 
-template <int NLR>
-__global__ __launch_bounds__(kPrepThreads) void k_scan(const PrepArgs a)
+__global__ __launch_bounds__(kPrepThreads) void k_scan(const ScanLaunch L)
 {
     __shared__ cplx mA[kPrepThreads], mB[kPrepThreads];  // composed maps
+    const JobDesc &J = L.jobs[blockIdx.x];
     const int tid = threadIdx.x;
-    const int M = a.M;
+    if (tid == 0)
+        *J.clock = *J.clock + 1u;
+    const int M = J.M;
     const int run = (M + kPrepThreads - 1) / kPrepThreads;
     const int b_lo = min(tid * run, M), b_hi = min(b_lo + run, M);
 #pragma unroll 1
-    for (int r = 0; r < NLR; ++r) {
-        cplx *seen = reinterpret_cast<cplx *>(a.seen) + (size_t)r * M;
-        const cplx *gap = reinterpret_cast<const cplx *>(a.gap) + (size_t)r * M;
-        const cplx *qc = reinterpret_cast<const cplx *>(a.qc) + (size_t)r * M;
-        const cplx *S = reinterpret_cast<const cplx *>(a.S) + (size_t)r * M;
+    for (int r = 0; r < J.nlr; ++r) {
+        cplx *seen = reinterpret_cast<cplx *>(J.seen) + (size_t)r * M;
+        const cplx *gap = reinterpret_cast<const cplx *>(J.gap) + (size_t)r * M;
+        const cplx *qc = reinterpret_cast<const cplx *>(J.qc) + (size_t)r * M;
+        const cplx *S = reinterpret_cast<const cplx *>(J.S) + (size_t)r * M;
         // 1. this thread's run: compose x -> G_b x + qc_b S_b over its bunches
         cplx A = {1.0, 0.0}, B = {0.0, 0.0};
         for (int b = b_lo; b < b_hi; ++b) {
@@ -529,7 +574,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_scan(const PrepArgs a)
             __syncthreads();
         }
         // 3. incoming phasor of this run, then replay the run
-        const cplx x0 = {a.phasor[2 * r], a.phasor[2 * r + 1]};
+        const cplx x0 = {J.phasor[2 * r], J.phasor[2 * r + 1]};
         cplx x = x0;
         if (tid > 0)
             x = cmuladd(mA[tid - 1], x0, mB[tid - 1]);
@@ -542,29 +587,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_scan(const PrepArgs a)
         __syncthreads();
         if (tid == kPrepThreads - 1) {
             const cplx xe = cmuladd(mA[tid], x0, mB[tid]);
-            a.phasor[2 * r] = xe.re;
-            a.phasor[2 * r + 1] = xe.im;
+            J.phasor[2 * r] = xe.re;
+            J.phasor[2 * r + 1] = xe.im;
         }
         __syncthreads();
     }
-}
-
-static __host__ __device__ inline int conv_chunks(const PrepArgs &a)
-{
-    return a.do_conv ? (a.nbins + kConvOut - 1) / kConvOut : 1;
-}
-
-template <int NLR>
-__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepArgs a)
-{
-    extern __shared__ double psm[];
-    const int nchunks = conv_chunks(a);
-    const int blk = blockIdx.x;
-    const int b = blk / nchunks, chunk = blk - b * nchunks;
-    if (chunk == 0)
-        finish_sums<NLR>(a, b);
-    if (a.do_conv)
-        conv_chunk(a, b, chunk, psm);
 }
 
 // ---------------------------------------------------------------------------
@@ -604,55 +631,53 @@ __global__ __launch_bounds__(256) void k_philox(int64_t n, const uint32_t *ctr, 
 // Launchers.
 // ---------------------------------------------------------------------------
 template <int NLR>
-static hipError_t push_n(const PushArgs &a, bool push, hipStream_t s)
+static hipError_t push_n(const PushLaunch &l, bool push, hipStream_t s)
 {
-    const dim3 grid(a.ntiles, a.M);
-    const size_t lds = push_lds_bytes(a.c.nbins, a.nsub);
+    const size_t lds = push_lds_bytes(l.nbins_max, l.nsub_max);
     if (push)
-        hipLaunchKernelGGL((k_push<NLR, true>), grid, dim3(kPushThreads), lds, s, a);
+        hipLaunchKernelGGL((k_push<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s, l);
     else
-        hipLaunchKernelGGL((k_push<NLR, false>), grid, dim3(kPushThreads), lds, s, a);
+        hipLaunchKernelGGL((k_push<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s, l);
     return hipGetLastError();
 }
 
-hipError_t launch_push(const PushArgs &a, int nlr, bool push, hipStream_t s)
+hipError_t launch_push(const PushLaunch &l, bool push, hipStream_t s)
 {
-    if (a.ntiles < 1 || a.M < 1 || a.ntiles > 2147483647 || a.M > 65535)
+    if (l.nitems < 1 || l.grid < 1)
         return hipErrorInvalidValue;
-    switch (nlr) {
-    case 0: return push_n<0>(a, push, s);
-    case 1: return push_n<1>(a, push, s);
-    case 2: return push_n<2>(a, push, s);
-    case 3: return push_n<3>(a, push, s);
-    case 4: return push_n<4>(a, push, s);
+    switch (l.nlr) {
+    case 0: return push_n<0>(l, push, s);
+    case 1: return push_n<1>(l, push, s);
+    case 2: return push_n<2>(l, push, s);
+    case 3: return push_n<3>(l, push, s);
+    case 4: return push_n<4>(l, push, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_prep(const PrepArgs &a, hipStream_t s)
+hipError_t launch_prep(const PrepLaunch &l, hipStream_t s)
 {
-    const int blocks = a.M * conv_chunks(a);
-    size_t lds = (size_t)2 * a.nbins * sizeof(double);
+    if (l.nitems < 1)
+        return hipErrorInvalidValue;
+    size_t lds = (size_t)2 * l.nbins_max * sizeof(double);
     if (lds == 0)
         lds = 16;
-    switch (a.nlr) {
-    case 0: hipLaunchKernelGGL((k_prep<0>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((k_prep<1>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_prep<2>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_prep<3>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_prep<4>), dim3(blocks), dim3(kPrepThreads), lds, s, a); break;
+    switch (l.nlr_max) {
+    case 0: hipLaunchKernelGGL((k_prep<0>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+    case 1: hipLaunchKernelGGL((k_prep<1>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+    case 2: hipLaunchKernelGGL((k_prep<2>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+    case 3: hipLaunchKernelGGL((k_prep<3>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+    case 4: hipLaunchKernelGGL((k_prep<4>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
     default: return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !a.do_scan || a.nlr == 0)
-        return e;
-    switch (a.nlr) {
-    case 1: hipLaunchKernelGGL((k_scan<1>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_scan<2>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_scan<3>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_scan<4>), dim3(1), dim3(kPrepThreads), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const ScanLaunch &l, hipStream_t s)
+{
+    if (l.njobs < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan, dim3(l.njobs), dim3(kPrepThreads), 0, s, l);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ import torch
 from . import _abi
 from ._abi import HC, Grid, Moments, Resonator, Ring
 
-__all__ = ["MbtError", "Tracker", "hc_flat_fraction", "philox4x32_10", "strerror"]
+__all__ = ["Batch", "MbtError", "Tracker", "hc_flat_fraction", "philox4x32_10", "strerror"]
 
 
 class MbtError(RuntimeError):
@@ -203,6 +203,10 @@ class Tracker:
         self._check(self._L.mbt_wake_potential(self._h, C.c_void_p(V.ctypes.data)))
         return V
 
+    def set_launch(self, nsub=0, push_grid=0):
+        """Push launch shape (sub-histograms, persistent workgroups; 0: defaults)."""
+        self._check(self._L.mbt_set_launch(self._h, int(nsub), int(push_grid)))
+
     def set_timing(self, every):
         self._check(self._L.mbt_set_timing(self._h, int(every)))
 
@@ -216,3 +220,75 @@ class Tracker:
         W = np.zeros(self.nbins)
         self._check(self._L.mbt_wake_table(self._h, C.c_void_p(W.ctypes.data)))
         return W
+
+
+class Batch:
+    """Several bound Trackers advanced together (mbt_batch_*): one launch of
+    each kernel per turn covers every bunch of every job."""
+
+    def __init__(self, trackers, stream=None, graph_turns=0, autotune=False):
+        self._L = _abi.lib()
+        self.trackers = list(trackers)
+        n = len(self.trackers)
+        self._jobs = (C.c_void_p * n)(*[t._h.value for t in self.trackers])
+        wb = C.c_size_t()
+        rc = self._L.mbt_batch_query_bytes(self._jobs, n, C.byref(wb))
+        if rc:
+            raise MbtError(rc, "mbt_batch_query_bytes")
+        dev = self.trackers[0].state.device
+        self.work = torch.empty(wb.value + 256, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        wp = (self.work.data_ptr() + 255) & ~255
+        self._h = C.c_void_p()
+        rc = self._L.mbt_batch_create(self._jobs, n, C.c_void_p(wp), wb.value,
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        if rc:
+            raise MbtError(rc, "mbt_batch_create")
+        self.configure(graph_turns, autotune)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.mbt_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise MbtError(rc, self._L.mbt_batch_last_error(self._h).decode())
+
+    def configure(self, graph_turns=0, autotune=False):
+        self._check(self._L.mbt_batch_configure(self._h, int(graph_turns), int(bool(autotune))))
+
+    def launch_info(self):
+        """[(long-range count, sub-histograms, workgroups)] per push group."""
+        ng = C.c_int32()
+        k = _abi.MBT_MAX_LONG_RANGE + 1
+        a, b, c = (C.c_int32 * k)(), (C.c_int32 * k)(), (C.c_int32 * k)()
+        self._check(self._L.mbt_batch_launch_info(self._h, C.byref(ng), a, b, c))
+        return [(a[i], b[i], c[i]) for i in range(ng.value)]
+
+    def track(self, nturns, profiles_stride=None, moments=True):
+        """Track every job nturns; returns a list of moment arrays [nturns][M_j][4]
+        (and a list of profile arrays when profiles_stride, a per-job list or
+        one int, is given; a stride of 0 leaves that job's profiles off)."""
+        n = len(self.trackers)
+        moms = [np.zeros((nturns, t.M, 4)) for t in self.trackers] if moments else None
+        strides = None
+        if profiles_stride is not None:
+            strides = (list(profiles_stride) if hasattr(profiles_stride, "__len__")
+                       else [profiles_stride] * n)
+        profs = None
+        if strides is not None:
+            profs = [np.zeros((-(-nturns // s), t.M, t.nbins), dtype=np.uint32) if s else None
+                     for s, t in zip(strides, self.trackers)]
+        out_p = (C.c_void_p * n)(*[m.ctypes.data for m in moms]) if moms else None
+        cnt_p = (C.c_void_p * n)(*[(p.ctypes.data if p is not None else None) for p in profs]) \
+            if profs else None
+        st_p = (C.c_int32 * n)(*[int(s) for s in strides]) if strides else None
+        self._check(self._L.mbt_batch_track(self._h, int(nturns), out_p, cnt_p, st_p))
+        return (moms, profs) if strides is not None else moms
