@@ -137,8 +137,8 @@ def main():
     push_ms, push_n, prep_ms, prep_n = t.get_timing()
     particles = w.M * w.N
     value = particles * args.steps / elapsed
-    push_avg_s = push_ms / 1e3 / max(push_n, 1)
-    achieved = BYTES_PER_PARTICLE_TURN * particles / push_avg_s / 1e9
+    push_avg_s = push_ms / 1e3 / push_n if push_n else float("nan")
+    achieved = BYTES_PER_PARTICLE_TURN * particles / push_avg_s / 1e9 if push_n else float("nan")
     traffic = traffic_from_profiles(particles)
     finite = bool(torch.isfinite(torch.from_numpy(mom[-1])).all())
 

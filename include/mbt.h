@@ -246,6 +246,26 @@ int mbt_get_timing(const mbt_ctx *ctx, double *push_ms, int64_t *push_launches,
  * MBT_EINVAL if the LDS image of the push would exceed 64 KiB. */
 int mbt_set_launch(mbt_ctx *ctx, int32_t nsub, int32_t push_grid);
 
+/* Arithmetic of the short-range wake potential V = qpp * T(W) * counts
+ * (Sec. 2.3), the product of the lower-triangular Toeplitz matrix of the wake
+ * table with the bunches' line densities:
+ *   MBT_WAKE_FP64   FP64 convolution on the vector units (default; the
+ *                   reference arithmetic, within 1e-13 of the FP64 oracle)
+ *   MBT_WAKE_FP32   matrix cores: W/s in FP32 (s a power of two near max|W|),
+ *                   counts exact in FP32 below 2^24, FP32 accumulation
+ *   MBT_WAKE_BF16X2 matrix cores: W/s as the sum of two BF16 terms, each
+ *                   count split exactly into 8-bit BF16 parts, FP32
+ *                   accumulation per part, parts combined in FP64
+ *   MBT_WAKE_BF16X3 as BF16X2 with three BF16 terms of W
+ * Particle coordinates, sums and phasors stay FP64 in every mode.  May be
+ * called at any time; the next call that tracks rebuilds the wake
+ * potential.  A job's mode is fixed while it belongs to a batch. */
+#define MBT_WAKE_FP64 0
+#define MBT_WAKE_FP32 1
+#define MBT_WAKE_BF16X2 2
+#define MBT_WAKE_BF16X3 3
+int mbt_set_wake_precision(mbt_ctx *ctx, int32_t mode);
+
 /* ---- Batches -------------------------------------------------------------
  * A batch advances several bound jobs (contexts on one device) together:
  * each turn is three launches that cover every bunch of every job -- the

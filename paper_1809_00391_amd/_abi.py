@@ -22,6 +22,10 @@ MBT_DEVICE = 1
 MBT_MAX_BINS = 4096
 MBT_MAX_SHORT_RANGE = 16
 MBT_MAX_LONG_RANGE = 4
+MBT_WAKE_FP64 = 0
+MBT_WAKE_FP32 = 1
+MBT_WAKE_BF16X2 = 2
+MBT_WAKE_BF16X3 = 3
 
 
 class Ring(C.Structure):
@@ -75,6 +79,7 @@ SIGNATURES = {
     "mbt_get_timing": (C.c_int, [_ctx, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                  _P(C.c_int64)]),
     "mbt_set_launch": (C.c_int, [_ctx, C.c_int32, C.c_int32]),
+    "mbt_set_wake_precision": (C.c_int, [_ctx, C.c_int32]),
     "mbt_batch_query_bytes": (C.c_int, [C.c_void_p, C.c_int32, _P(C.c_size_t)]),
     "mbt_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                    _P(C.c_void_p)]),

@@ -19,6 +19,22 @@ namespace mbt {
 // and P2 = pi/2 - P1, each step one FMA, then a quadrant swap.  Arguments
 // beyond 1e5 (never reached by particles near a bucket) use the library.
 // ---------------------------------------------------------------------------
+// One Horner step p*z + c, rounded once.  On the device it is spelled as a
+// single three-operand v_fma_f64: for a coefficient held in a vector
+// register the compiler otherwise emits the accumulating form, which first
+// copies the coefficient into the destination (one extra instruction per
+// step).  The result is the same correctly rounded FMA either way.
+__host__ __device__ __forceinline__ double horner(double p, double z, double c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r;
+    __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "v"(c));
+    return r;
+#else
+    return fma(p, z, c);
+#endif
+}
+
 constexpr double kPio2Hi = 1.5707963267948966;     // double nearest pi/2
 constexpr double kPio2Lo = 6.123233995736766e-17;  // pi/2 - kPio2Hi
 constexpr double kTwoOverPi = 0.6366197723675814;
@@ -27,21 +43,21 @@ __host__ __device__ __forceinline__ void sincos_poly(double r, double &s, double
 {
     const double z = r * r;
     double ps = -1.0 / 1307674368000.0;           // -1/15!
-    ps = fma(ps, z, 1.0 / 6227020800.0);          //  1/13!
-    ps = fma(ps, z, -1.0 / 39916800.0);           // -1/11!
-    ps = fma(ps, z, 1.0 / 362880.0);              //  1/9!
-    ps = fma(ps, z, -1.0 / 5040.0);               // -1/7!
-    ps = fma(ps, z, 1.0 / 120.0);                 //  1/5!
-    ps = fma(ps, z, -1.0 / 6.0);                  // -1/3!
+    ps = horner(ps, z, 1.0 / 6227020800.0);          //  1/13!
+    ps = horner(ps, z, -1.0 / 39916800.0);           // -1/11!
+    ps = horner(ps, z, 1.0 / 362880.0);              //  1/9!
+    ps = horner(ps, z, -1.0 / 5040.0);               // -1/7!
+    ps = horner(ps, z, 1.0 / 120.0);                 //  1/5!
+    ps = horner(ps, z, -1.0 / 6.0);                  // -1/3!
     s = fma(r * z, ps, r);
     double pc = 1.0 / 20922789888000.0;           //  1/16!
-    pc = fma(pc, z, -1.0 / 87178291200.0);        // -1/14!
-    pc = fma(pc, z, 1.0 / 479001600.0);           //  1/12!
-    pc = fma(pc, z, -1.0 / 3628800.0);            // -1/10!
-    pc = fma(pc, z, 1.0 / 40320.0);               //  1/8!
-    pc = fma(pc, z, -1.0 / 720.0);                // -1/6!
-    pc = fma(pc, z, 1.0 / 24.0);                  //  1/4!
-    pc = fma(pc, z, -0.5);                        // -1/2!
+    pc = horner(pc, z, -1.0 / 87178291200.0);        // -1/14!
+    pc = horner(pc, z, 1.0 / 479001600.0);           //  1/12!
+    pc = horner(pc, z, -1.0 / 3628800.0);            // -1/10!
+    pc = horner(pc, z, 1.0 / 40320.0);               //  1/8!
+    pc = horner(pc, z, -1.0 / 720.0);                // -1/6!
+    pc = horner(pc, z, 1.0 / 24.0);                  //  1/4!
+    pc = fma(pc, z, -0.5);                           // -1/2! (inline constant)
     c = fma(z, pc, 1.0);
 }
 
@@ -56,16 +72,22 @@ __host__ __device__ __forceinline__ void quadrant(int q, double sr, double cr, d
 
 // Library sine and cosine for the rare huge argument, kept out of line so
 // the per-particle loop stays small.
-__host__ __device__ __noinline__ void sincos_libm(double x, double &s, double &c)
+// Returned by value: an out-parameter of a call that is not inlined would
+// force the caller's results through scratch memory on every path.
+struct SinCos {
+    double s, c;
+};
+__host__ __device__ __noinline__ SinCos sincos_libm(double x)
 {
-    s = sin(x);
-    c = cos(x);
+    return SinCos{sin(x), cos(x)};
 }
 
 __host__ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c)
 {
     if (!(fabs(x) < 1e5)) {
-        sincos_libm(x, s, c);
+        const SinCos r = sincos_libm(x);
+        s = r.s;
+        c = r.c;
         return;
     }
     const double k = rint(x * kTwoOverPi);
@@ -95,8 +117,8 @@ __host__ __device__ __forceinline__ double exp_small(double y)
 {
     if (fabs(y) < 1e-3) {
         double p = 1.0 / 120.0;
-        p = fma(p, y, 1.0 / 24.0);
-        p = fma(p, y, 1.0 / 6.0);
+        p = horner(p, y, 1.0 / 24.0);
+        p = horner(p, y, 1.0 / 6.0);
         p = fma(p, y, 0.5);
         p = fma(p, y, 1.0);
         return fma(p, y, 1.0);
@@ -141,14 +163,14 @@ __host__ __device__ __forceinline__ double log_unit(double u)
     const double s = (m - 1.0) / (m + 1.0);
     const double z = s * s;
     double p = 1.0 / 19.0;
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    p = horner(p, z, 1.0 / 17.0);
+    p = horner(p, z, 1.0 / 15.0);
+    p = horner(p, z, 1.0 / 13.0);
+    p = horner(p, z, 1.0 / 11.0);
+    p = horner(p, z, 1.0 / 9.0);
+    p = horner(p, z, 1.0 / 7.0);
+    p = horner(p, z, 1.0 / 5.0);
+    p = horner(p, z, 1.0 / 3.0);
     const double lm = fma(2.0 * s * z, p, 2.0 * s);
     const double ln2_hi = 0.693147180369123816490;    // ln 2 to 32 bits
     const double ln2_lo = 1.90821492927058770002e-10; // ln 2 - ln2_hi

@@ -51,6 +51,25 @@ bool res_valid(const mbt_resonator &r)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// BF16 (the upper 16 bits of an IEEE single) nearest to x, ties to even,
+// through the FP32 rounding of x; and its value.
+uint16_t bf16_nearest(double x)
+{
+    const float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
 int floor_pow2(size_t x)
 {
     int p = 1;
@@ -63,10 +82,10 @@ constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS of one push workgroup
 
 // Offsets of every workspace region for a given job shape.
 struct Layout {
-    size_t desc, items_push, items_prep, clock, status;
+    size_t desc, items_push, items_prep, items_wake, clock, status, Wbf, Wf32;
     size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, mom, prof;
     size_t total;
-    int mom_slots, prof_slots, ntiles, nchunks;
+    int mom_slots, prof_slots, ntiles, nchunks, nwake;
     int64_t ld;
     size_t state_bytes;
 };
@@ -78,6 +97,7 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     L.ld = (N + kRowAlign - 1) / kRowAlign * kRowAlign;
     L.ntiles = (int)((N + kTile - 1) / kTile);
     L.nchunks = conv_chunks(nb);
+    L.nwake = nb > 0 ? ((M + kWakeBunches - 1) / kWakeBunches) * ((nb + kWakeBins - 1) / kWakeBins) : 0;
     // output rings: powers of two, about 16 MB each at most
     const size_t moment_row = (size_t)M * 4 * sizeof(double);
     L.mom_slots = floor_pow2(std::max<size_t>(16, std::min<size_t>(1024, (16u << 20) / moment_row)));
@@ -93,9 +113,12 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     L.desc = take(sizeof(JobDesc));
     L.items_push = take((size_t)M * L.ntiles * sizeof(Item));
     L.items_prep = take((size_t)M * L.nchunks * sizeof(Item));
+    L.items_wake = take((size_t)std::max(L.nwake, 1) * sizeof(Item));
     L.clock = take(sizeof(uint32_t));
     L.status = take(sizeof(uint32_t));
     L.W = take((size_t)nbx * sizeof(double));
+    L.Wbf = take((size_t)3 * nbx * sizeof(uint16_t));
+    L.Wf32 = take((size_t)nbx * sizeof(float));
     L.V = take((size_t)M * nbx * sizeof(double));
     L.counts = take((size_t)2 * M * nbx * sizeof(uint32_t));
     L.partials = take((size_t)M * L.ntiles * kPartStride * sizeof(double));
@@ -185,6 +208,10 @@ struct mbt_ctx {
     RingOut mom, prof;         // pinned staging of the output rings
     // launch shape (neither changes a result bit)
     int nsub = 0, push_grid = 0;
+    // arithmetic of the wake potential (WakeMode) and its tables
+    int wake_mode = kWakeFP64;
+    int count_parts = 1;
+    double wake_scale = 1.0;
     Timer timer;
     // run state
     bool have_particles = false;
@@ -288,6 +315,11 @@ JobDesc job_desc(const mbt_ctx *c, uint32_t base, int prof_stride)
     d.base = base;
     d.key0 = (uint32_t)c->seed;
     d.key1 = (uint32_t)(c->seed >> 32);
+    d.wake_mode = c->sr_on ? c->wake_mode : kWakeFP64;
+    d.count_parts = c->count_parts;
+    d.wake_scale = c->wake_scale;
+    d.Wbf = c->w<uint16_t>(c->L.Wbf);
+    d.Wf32 = c->w<float>(c->L.Wf32);
     d.W = c->w<double>(c->L.W);
     d.qpp = c->w<double>(c->L.qpp);
     d.gap = c->w<double>(c->L.gap);
@@ -322,18 +354,34 @@ void prep_items(const mbt_ctx *c, int job, std::vector<Item> &out)
             out.push_back(Item{(uint16_t)job, (uint16_t)b, (uint32_t)k});
 }
 
+// Wake items of a job: (job, 16-bunch tile, 64-bin tile).
+void wake_items(const mbt_ctx *c, int job, std::vector<Item> &out)
+{
+    const int nb = c->nbins();
+    if (nb == 0)
+        return;
+    for (int bt = 0; bt < (c->M + kWakeBunches - 1) / kWakeBunches; ++bt)
+        for (int kt = 0; kt < (nb + kWakeBins - 1) / kWakeBins; ++kt)
+            out.push_back(Item{(uint16_t)job, (uint16_t)bt, (uint32_t)kt});
+}
+
 // Launch tables of a set of jobs whose descriptors and item lists are in
 // device memory.  Push items are grouped by the number of long-range
 // resonators (a template parameter of the push).
 struct Group {
     int item0 = 0, nitems = 0, nlr = 0, nbins_max = 0, nsub_max = 0, grid = 0;
 };
+struct WakeGroup {
+    int item0 = 0, nitems = 0, mode = 0, nbins_max = 0;
+};
 struct Engine {
     const JobDesc *jobs = nullptr;
     const Item *push_items = nullptr;
     const Item *prep_items = nullptr;
+    const Item *wake_items = nullptr;
     int njobs = 0, nprep = 0, nlr_max = 0, nbins_max = 0;
     std::vector<Group> groups;
+    std::vector<WakeGroup> wakes;  // jobs whose wake potential comes from k_wake
 };
 
 PushLaunch push_launch(const Engine &e, const Group &g)
@@ -359,6 +407,7 @@ hipError_t enqueue_push(const Engine &e, bool push, hipStream_t s)
     return hipSuccess;
 }
 
+// The between-turn work after a push: sums, histograms, wake potential.
 hipError_t enqueue_prep(const Engine &e, hipStream_t s)
 {
     PrepLaunch l{};
@@ -368,7 +417,19 @@ hipError_t enqueue_prep(const Engine &e, hipStream_t s)
     l.nlr_max = e.nlr_max;
     l.nbins_max = e.nbins_max;
     l.do_conv = 1;
-    return launch_prep(l, s);
+    hipError_t r = launch_prep(l, s);
+    for (const WakeGroup &g : e.wakes) {
+        if (r != hipSuccess)
+            break;
+        WakeLaunch w{};
+        w.jobs = e.jobs;
+        w.items = e.wake_items + g.item0;
+        w.nitems = g.nitems;
+        w.mode = g.mode;
+        w.nbins_max = g.nbins_max;
+        r = launch_wake(w, s);
+    }
+    return r;
 }
 
 hipError_t enqueue_scan(const Engine &e, hipStream_t s)
@@ -423,6 +484,14 @@ Engine single_engine(const mbt_ctx *c)
     g.nsub_max = c->nsub;
     g.grid = c->push_grid;
     e.groups.push_back(g);
+    e.wake_items = c->w<Item>(c->L.items_wake);
+    if (c->sr_on && c->wake_mode != kWakeFP64) {
+        WakeGroup w;
+        w.nitems = c->L.nwake;
+        w.mode = c->wake_mode;
+        w.nbins_max = c->nbins();
+        e.wakes.push_back(w);
+    }
     return e;
 }
 
@@ -859,11 +928,38 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
             qc[ix + 1] = qpp[b] * ci;
         }
     }
-    std::vector<Item> pitems, citems;
+    std::vector<Item> pitems, citems, witems;
     pitems.reserve((size_t)M * L.ntiles);
     citems.reserve((size_t)M * L.nchunks);
     push_items(c, 0, pitems);
     prep_items(c, 0, citems);
+    wake_items(c, 0, witems);
+    // Matrix-core tables of the wake: W / s with s a power of two near max |W|,
+    // as FP32 and as three BF16 terms (each the BF16 nearest to what the
+    // previous ones leave).  Bin counts stay below 2^(8 count_parts).
+    std::vector<uint16_t> wbf((size_t)3 * nbx, 0);
+    std::vector<float> wf((size_t)nbx, 0.f);
+    {
+        double wmax = 0.0;
+        for (double v : W)
+            wmax = std::max(wmax, std::fabs(v));
+        int e = 0;
+        if (wmax > 0.0)
+            std::frexp(wmax, &e);  // wmax = f 2^e, f in [1/2, 1)
+        c->wake_scale = wmax > 0.0 ? std::ldexp(1.0, e) : 1.0;
+        for (int k = 0; k < nbx; ++k) {
+            double rest = W[k] / c->wake_scale;
+            wf[k] = (float)rest;
+            for (int q = 0; q < 3; ++q) {
+                const uint16_t h = bf16_nearest(rest);
+                wbf[(size_t)q * nbx + k] = h;
+                rest -= bf16_value(h);
+            }
+        }
+        c->count_parts = 1;
+        while (c->count_parts < 4 && (double)N >= std::ldexp(1.0, 8 * c->count_parts))
+            ++c->count_parts;
+    }
     HIPCHK(c, hipMemsetAsync(c->work, 0, L.total, c->stream_h));
     HIPCHK(c, hipMemcpyAsync(c->w<double>(L.W), W.data(), W.size() * sizeof(double),
                              hipMemcpyHostToDevice, c->stream_h));
@@ -878,6 +974,13 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
     HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_push), pitems.data(), pitems.size() * sizeof(Item),
                              hipMemcpyHostToDevice, c->stream_h));
     HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_prep), citems.data(), citems.size() * sizeof(Item),
+                             hipMemcpyHostToDevice, c->stream_h));
+    if (!witems.empty())
+        HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_wake), witems.data(), witems.size() * sizeof(Item),
+                                 hipMemcpyHostToDevice, c->stream_h));
+    HIPCHK(c, hipMemcpyAsync(c->w<uint16_t>(L.Wbf), wbf.data(), wbf.size() * sizeof(uint16_t),
+                             hipMemcpyHostToDevice, c->stream_h));
+    HIPCHK(c, hipMemcpyAsync(c->w<float>(L.Wf32), wf.data(), wf.size() * sizeof(float),
                              hipMemcpyHostToDevice, c->stream_h));
     HIPCHK(c, hipMemsetAsync(d_state, 0, L.state_bytes, c->stream_h));
     HIPCHK(c, hipStreamSynchronize(c->stream_h));
@@ -1113,6 +1216,18 @@ int mbt_get_timing(const mbt_ctx *c, double *push_ms, int64_t *push_launches, do
     return MBT_OK;
 }
 
+int mbt_set_wake_precision(mbt_ctx *c, int32_t mode)
+{
+    if (!c)
+        return MBT_EINVAL;
+    if (mode < MBT_WAKE_FP64 || mode > MBT_WAKE_BF16X3)
+        return fail(c, MBT_EINVAL, "unknown wake precision %d", mode);
+    if (mode != c->wake_mode)
+        c->dirty = true;  // the stored wake potential used the other arithmetic
+    c->wake_mode = mode;
+    return MBT_OK;
+}
+
 int mbt_set_launch(mbt_ctx *c, int32_t nsub, int32_t push_grid)
 {
     if (!c)
@@ -1151,8 +1266,9 @@ struct mbt_batch {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;   // private stream that graphs are captured on
     JobDesc *pin_desc = nullptr; // pinned [njobs]
-    size_t off_push = 0, off_prep = 0, total = 0;
+    size_t off_push = 0, off_prep = 0, off_wake = 0, total = 0;
     Engine eng;
+    std::vector<int> wake_modes;  // each job's wake arithmetic when the batch was made
     int graph_turns = 0;
     bool autotune = false, tuned = false;
     hipGraph_t graph = nullptr;
@@ -1163,18 +1279,22 @@ struct mbt_batch {
 
 namespace {
 
-size_t batch_layout(mbt_ctx *const *jobs, int n, size_t *off_push, size_t *off_prep)
+size_t batch_layout(mbt_ctx *const *jobs, int n, size_t *off_push, size_t *off_prep,
+                    size_t *off_wake)
 {
-    size_t np = 0, nc = 0;
+    size_t np = 0, nc = 0, nw = 0;
     for (int j = 0; j < n; ++j) {
         np += (size_t)jobs[j]->M * jobs[j]->L.ntiles;
         nc += (size_t)jobs[j]->M * jobs[j]->L.nchunks;
+        nw += (size_t)jobs[j]->L.nwake;
     }
     size_t o = align256((size_t)n * sizeof(JobDesc));
     *off_push = o;
     o = align256(o + np * sizeof(Item));
     *off_prep = o;
     o = align256(o + nc * sizeof(Item));
+    *off_wake = o;
+    o = align256(o + std::max<size_t>(nw, 1) * sizeof(Item));
     return o;
 }
 
@@ -1388,8 +1508,8 @@ int mbt_batch_query_bytes(mbt_ctx *const *jobs, int32_t njobs, size_t *work_byte
     for (int j = 0; j < njobs; ++j)
         if (!jobs[j] || !jobs[j]->bound)
             return MBT_ESTATE;
-    size_t a, b;
-    *work_bytes = batch_layout(jobs, njobs, &a, &b);
+    size_t a, b, w;
+    *work_bytes = batch_layout(jobs, njobs, &a, &b, &w);
     return MBT_OK;
 }
 
@@ -1420,7 +1540,7 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
     B->jobs.assign(jobs, jobs + njobs);
     B->work = reinterpret_cast<unsigned char *>(d_work);
     B->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep);
+    B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep, &B->off_wake);
     // items grouped by long-range count, jobs in the order given
     std::vector<Item> pitems, citems;
     Engine &e = B->eng;
@@ -1444,6 +1564,22 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
         prep_items(jobs[j], j, citems);
         e.nlr_max = std::max(e.nlr_max, jobs[j]->nlr());
         e.nbins_max = std::max(e.nbins_max, jobs[j]->nbins());
+        B->wake_modes.push_back(jobs[j]->wake_mode);
+    }
+    // wake items grouped by arithmetic (a template parameter of k_wake)
+    std::vector<Item> witems;
+    for (int mode = kWakeFP32; mode <= kWakeBF16x3; ++mode) {
+        WakeGroup g;
+        g.item0 = (int)witems.size();
+        g.mode = mode;
+        for (int j = 0; j < njobs; ++j)
+            if (jobs[j]->sr_on && jobs[j]->wake_mode == mode) {
+                wake_items(jobs[j], j, witems);
+                g.nbins_max = std::max(g.nbins_max, jobs[j]->nbins());
+            }
+        g.nitems = (int)witems.size() - g.item0;
+        if (g.nitems > 0)
+            e.wakes.push_back(g);
     }
     if (pitems.size() > (size_t)INT32_MAX || citems.size() > (size_t)INT32_MAX) {
         delete B;
@@ -1452,6 +1588,7 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
     e.jobs = reinterpret_cast<const JobDesc *>(B->work);
     e.push_items = reinterpret_cast<const Item *>(B->work + B->off_push);
     e.prep_items = reinterpret_cast<const Item *>(B->work + B->off_prep);
+    e.wake_items = reinterpret_cast<const Item *>(B->work + B->off_wake);
     e.njobs = njobs;
     e.nprep = (int)citems.size();
     auto bail = [&](hipError_t r) {
@@ -1468,6 +1605,9 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
                             hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
         (r = hipMemcpyAsync(B->work + B->off_prep, citems.data(), citems.size() * sizeof(Item),
                             hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
+        (!witems.empty() &&
+         (r = hipMemcpyAsync(B->work + B->off_wake, witems.data(), witems.size() * sizeof(Item),
+                             hipMemcpyHostToDevice, B->stream)) != hipSuccess) ||
         (r = hipStreamSynchronize(B->stream)) != hipSuccess)
         return bail(r);
     *out = B;
@@ -1534,6 +1674,8 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
             return fail(B, MBT_EINVAL, "job %d: turn counter would pass 2^32", j);
         if (counts && counts[j] && (!c->sr_on || !stride || stride[j] < 1))
             return fail(B, MBT_EINVAL, "job %d: profiles need a grid and stride >= 1", j);
+        if (c->wake_mode != B->wake_modes[j])
+            return fail(B, MBT_ESTATE, "job %d: wake precision changed after the batch was made", j);
     }
     if (nturns == 0)
         return MBT_OK;

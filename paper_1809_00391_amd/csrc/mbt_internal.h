@@ -64,6 +64,11 @@ struct JobDesc {
     int prof_slots;           // profile ring rows (power of two)
     uint32_t base;            // first turn of the present call: ring rows count from it
     uint32_t key0, key1;      // Philox key = seed
+    int wake_mode;            // 0: FP64 convolution in the prep; else k_wake (WakeMode)
+    int count_parts;          // 8-bit parts of a bin count (< 2^(8 count_parts))
+    double wake_scale;        // power of two: the MFMA tables hold W / wake_scale
+    const uint16_t *Wbf;      // [3][nbins] BF16 parts of W / wake_scale (hi, lo, lo2)
+    const float *Wf32;        // [nbins] W / wake_scale rounded to FP32
     const double *W;          // [nbins] wake table
     const double *qpp;        // [M] charge per macro-particle
     const double *gap;        // [nlr][M][2] rotation into bunch b's bucket
@@ -88,6 +93,14 @@ struct Item {
     uint32_t part;
 };
 
+// Arithmetic of the short-range wake potential.
+enum WakeMode {
+    kWakeFP64 = 0,    // FP64 convolution on the vector units (the reference arithmetic)
+    kWakeFP32 = 1,    // FP32 W x exact FP32 counts on MFMA, FP32 accumulation
+    kWakeBF16x2 = 2,  // W split in two BF16 terms x counts split in exact 8-bit BF16 parts
+    kWakeBF16x3 = 3,  // as above with three BF16 terms of W
+};
+
 // Launch descriptors.
 struct PushLaunch {
     const JobDesc *jobs;
@@ -106,6 +119,13 @@ struct PrepLaunch {
     int nbins_max;
     int do_conv;              // 0: moments only (the state at the end of a call)
 };
+struct WakeLaunch {
+    const JobDesc *jobs;
+    const Item *items;        // (job, 16-bunch tile, 64-bin tile)
+    int nitems;
+    int mode;                 // WakeMode other than kWakeFP64; every job of the items has it
+    int nbins_max;
+};
 struct ScanLaunch {
     const JobDesc *jobs;
     int njobs;
@@ -115,6 +135,7 @@ struct ScanLaunch {
 hipError_t launch_push(const PushLaunch &l, bool push, hipStream_t s);
 hipError_t launch_prep(const PrepLaunch &l, hipStream_t s);
 hipError_t launch_scan(const ScanLaunch &l, hipStream_t s);
+hipError_t launch_wake(const WakeLaunch &l, hipStream_t s);
 hipError_t launch_init_gauss(double *tau, double *delta, int64_t ld, int64_t N, int M,
                              const uint32_t *stream, double sig_tau, double sig_delta,
                              uint32_t key0, uint32_t key1, hipStream_t s);
@@ -122,5 +143,7 @@ hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t
                          uint32_t *out, hipStream_t s);
 size_t push_lds_bytes(int nbins, int nsub);
 int conv_chunks(int nbins);
+constexpr int kWakeBins = 64;     // bins per k_wake workgroup (16 per wavefront)
+constexpr int kWakeBunches = 16;  // bunches per k_wake workgroup
 
 }  // namespace mbt

@@ -23,6 +23,8 @@
 // stores, and one Philox block gives both particles of a pair their noise.
 // No floating-point atomics: all floating sums are fixed-order tile partials,
 // so a run is bit-reproducible; histograms use integer atomics.
+#include <algorithm>
+
 #include "mbt_internal.h"
 #include "mbt_fastmath.h"
 
@@ -220,6 +222,13 @@ __device__ __forceinline__ void pair_compute(const MapConst &c, uint32_t key0, u
         epilogue<NLR>(c, hist_w, t1, d1, acc);
 }
 
+// Pointers known to address global memory: loads and stores through them
+// compile to global (not flat) instructions, which the compiler cannot infer
+// for pointers read from a descriptor.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+typedef double dvec2 __attribute__((ext_vector_type(2)));  // one 16-byte access
+
 // A wavefront-uniform copy of *p held in scalar registers: the descriptors
 // live in memory the kernels also write, so the compiler cannot prove them
 // unchanged and would otherwise keep every field in vector registers.
@@ -246,17 +255,26 @@ __device__ __forceinline__ T load_uniform(const T *p)
 // n - 1.  Full tiles run a loop without bounds checks that loads the next
 // pair before computing the current one.
 // ---------------------------------------------------------------------------
+// Occupancy: without long-range resonators the push fits in 128 registers,
+// which allows four workgroups (four waves per SIMD) per compute unit; with
+// them, forcing that would spill.
+template <int NLR>
+constexpr int push_min_blocks() { return NLR == 0 ? 4 : 1; }
+
 template <int NLR, bool PUSH>
-__global__ __launch_bounds__(kPushThreads) void k_push(const PushLaunch L)
+__global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
+    const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
+    const int grid)
 {
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     constexpr int NP = 4 + 2 * NLR;
 
-    for (int it = blockIdx.x; it < L.nitems; it += L.grid) {
-        const Item item = load_uniform(L.items + it);
-        const JobDesc J = load_uniform(L.jobs + item.job);
+    for (int it = blockIdx.x; it < nitems; it += grid) {
+        // descriptors are read-only here, so these loads are scalar
+        const Item item = items[it];
+        const JobDesc &J = jobs[item.job];
         const MapConst &c = J.c;
         const int nb = c.nbins, nbx = nb > 0 ? nb : 1;
         const int b = item.bunch;
@@ -283,8 +301,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushLaunch L)
             seen[r][1] = J.seen[((size_t)r * J.M + b) * 2 + 1] * c.inv_E0;
         }
         const uint32_t stream = J.stream[b];
-        double *tau = J.tau + (size_t)b * J.ld;
-        double *del = J.delta + (size_t)b * J.ld;
+        const gptr<double> tau = (gptr<double>)(J.tau + (size_t)b * J.ld);
+        const gptr<double> del = (gptr<double>)(J.delta + (size_t)b * J.ld);
         double acc[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i)
@@ -294,21 +312,21 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushLaunch L)
         const uint32_t pair0 = tile * (uint32_t)(kPushThreads * kPairsPerThread);
         if ((int64_t)(pair0 + kPushThreads * kPairsPerThread) * 2 <= J.N) {
             uint32_t p = pair0 + (uint32_t)tid;
-            double2 tv = *reinterpret_cast<const double2 *>(tau + 2u * p);
-            double2 dv = *reinterpret_cast<const double2 *>(del + 2u * p);
+            dvec2 tv = *reinterpret_cast<const gptr<dvec2>>(tau + 2u * p);
+            dvec2 dv = *reinterpret_cast<const gptr<dvec2>>(del + 2u * p);
 #pragma unroll 1
             for (int s = 0; s < kPairsPerThread; ++s) {
-                double2 tn = tv, dn = dv;
+                dvec2 tn = tv, dn = dv;
                 if (s + 1 < kPairsPerThread) {
-                    tn = *reinterpret_cast<const double2 *>(tau + 2u * (p + kPushThreads));
-                    dn = *reinterpret_cast<const double2 *>(del + 2u * (p + kPushThreads));
+                    tn = *reinterpret_cast<const gptr<dvec2>>(tau + 2u * (p + kPushThreads));
+                    dn = *reinterpret_cast<const gptr<dvec2>>(del + 2u * (p + kPushThreads));
                 }
                 double t0 = tv.x, t1 = tv.y, d0 = dv.x, d1 = dv.y;
                 pair_compute<NLR, PUSH>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, true,
                                         t0, t1, d0, d1, acc);
                 if (PUSH) {
-                    *reinterpret_cast<double2 *>(tau + 2u * p) = make_double2(t0, t1);
-                    *reinterpret_cast<double2 *>(del + 2u * p) = make_double2(d0, d1);
+                    *reinterpret_cast<gptr<dvec2>>(tau + 2u * p) = dvec2{t0, t1};
+                    *reinterpret_cast<gptr<dvec2>>(del + 2u * p) = dvec2{d0, d1};
                 }
                 tv = tn;
                 dv = dn;
@@ -325,8 +343,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushLaunch L)
                 const bool two = j0 < n_last;
                 double t0, t1 = 0.0, d0, d1 = 0.0;
                 if (two) {
-                    const double2 tv = *reinterpret_cast<const double2 *>(tau + j0);
-                    const double2 dv = *reinterpret_cast<const double2 *>(del + j0);
+                    const dvec2 tv = *reinterpret_cast<const gptr<dvec2>>(tau + j0);
+                    const dvec2 dv = *reinterpret_cast<const gptr<dvec2>>(del + j0);
                     t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
                 } else {
                     t0 = tau[j0];
@@ -336,8 +354,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(const PushLaunch L)
                                         t0, t1, d0, d1, acc);
                 if (PUSH) {
                     if (two) {
-                        *reinterpret_cast<double2 *>(tau + j0) = make_double2(t0, t1);
-                        *reinterpret_cast<double2 *>(del + j0) = make_double2(d0, d1);
+                        *reinterpret_cast<gptr<dvec2>>(tau + j0) = dvec2{t0, t1};
+                        *reinterpret_cast<gptr<dvec2>>(del + j0) = dvec2{d0, d1};
                     } else {
                         tau[j0] = t0;
                         del[j0] = d0;
@@ -507,8 +525,145 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
     const uint32_t clock = *J.clock;
     if (item.part == 0)
         finish_sums<NLR>(J, item.bunch, clock);
-    if (L.do_conv && J.c.sr_on)
-        conv_chunk(J, item.bunch, (int)item.part, clock, psm);
+    if (L.do_conv && J.c.sr_on) {
+        if (J.wake_mode == kWakeFP64) {
+            conv_chunk(J, item.bunch, (int)item.part, clock, psm);
+        } else {
+            // the wake potential comes from k_wake; clear what the push fills next
+            const int nb = J.c.nbins;
+            const int k0 = (int)item.part * kConvOut, k1 = min(k0 + kConvOut, nb);
+            uint32_t *cclr = J.counts + ((size_t)(clock & 1u) * J.M + item.bunch) * nb;
+            for (int k = k0 + threadIdx.x; k < k1; k += kPrepThreads)
+                cclr[k] = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_wake: the short-range wake potential of all bunches as one product of
+// the lower-triangular Toeplitz matrix T[k][m] = W[k - m] (Sec. 2.3) with
+// the matrix of line densities C[m][b] (bin m, bunch b), on the matrix
+// cores: V[b][k] = qpp_b sum_m T[k][m] C[m][b].
+//   FP32:   W / s rounded to FP32, counts exact in FP32 (below 2^24),
+//           v_mfma_f32_16x16x4_f32, FP32 accumulation.
+//   BF16xn: W / s = W_0 + W_1 (+ W_2), each term BF16 (8 significant bits,
+//           so the residual after n terms is about 2^-9n of W); every count
+//           c = sum_p c_p 2^(8p) with 8-bit parts c_p, each exact in BF16;
+//           v_mfma_f32_16x16x16_bf16 accumulates sum_q T_q C_p in FP32 per
+//           part p; the parts are combined in FP64.
+// s is a power of two near max |W|, so the tables are O(1).  A workgroup
+// covers 64 bins x 16 bunches, one 16 x 16 output tile per wavefront; the
+// reduction over m stops at the diagonal.  MFMA 16x16 operand layout (lane l,
+// element r): A[l % 16][4 (l / 16) + r], B[4 (l / 16) + r][l % 16], and the
+// result C[4 (l / 16) + r][l % 16]; for the f32 form with K = 4,
+// A[l % 16][l / 16] and B[l / 16][l % 16].
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// An integer in [0, 256] as BF16: its float has at most 8 significant bits,
+// so the upper half of the float is the exact BF16.
+__device__ __forceinline__ short small_int_bf16(uint32_t v)
+{
+    return (short)(__float_as_uint((float)v) >> 16);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
+{
+    extern __shared__ double wsm[];
+    const Item item = L.items[blockIdx.x];
+    const JobDesc &J = L.jobs[item.job];
+    const int nb = J.c.nbins, M = J.M;
+    const int b0 = (int)item.bunch * kWakeBunches;
+    const int kt = (int)item.part * kWakeBins;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t clock = *J.clock;
+    const uint32_t *cnt = J.counts + (size_t)((clock + 1u) & 1u) * M * nb;
+    constexpr int NW = MODE == kWakeFP32 ? 1 : (MODE == kWakeBF16x2 ? 2 : 3);
+
+    // W (or its parts) at distances [0, kmax) in LDS
+    const int kmax = min(nb, kt + kWakeBins);
+    float *wf = reinterpret_cast<float *>(wsm);
+    uint16_t *wb = reinterpret_cast<uint16_t *>(wsm);
+    if (MODE == kWakeFP32) {
+        for (int k = tid; k < kmax; k += 256)
+            wf[k] = J.Wf32[k];
+    } else {
+        for (int q = 0; q < NW; ++q)
+            for (int k = tid; k < kmax; k += 256)
+                wb[q * kmax + k] = J.Wbf[(size_t)q * nb + k];
+    }
+    __syncthreads();
+    const int kb = kt + 16 * wave;  // first bin of this wavefront's tile
+    if (kb >= nb)
+        return;
+    const int i = lane & 15, g = lane >> 4;
+    const int b = b0 + i;  // bunch of this lane's column
+    const bool bok = b < M;
+    const uint32_t *crow = cnt + (size_t)(bok ? b : 0) * nb;
+    const bool rok = kb + i < nb;  // row of this lane's A operand inside the grid
+    floatx4 acc[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int mend = min(nb, kb + 16);
+    const int np = J.count_parts;
+    for (int m0 = 0; m0 < mend; m0 += 16) {
+        if (MODE == kWakeFP32) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int m = m0 + 4 * s + g;
+                const int d = kb + i - m;
+                const float a = (rok && d >= 0) ? wf[d] : 0.f;
+                const float c = (bok && m < nb) ? (float)crow[m] : 0.f;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, c, acc[0], 0, 0, 0);
+            }
+        } else {
+            const int mg = m0 + 4 * g;
+            uint32_t c[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                c[r] = (bok && mg + r < nb) ? crow[mg + r] : 0u;
+            bf16x4 a[NW];
+            const int d0 = kb + i - mg;
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    a[q][r] = (rok && d0 - r >= 0) ? (short)wb[q * kmax + d0 - r] : (short)0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                if (p >= np)
+                    break;
+                bf16x4 bp;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    bp[r] = small_int_bf16((c[r] >> (8 * p)) & 255u);
+#pragma unroll
+                for (int q = 0; q < NW; ++q)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], bp, acc[p], 0, 0, 0);
+            }
+        }
+    }
+    if (!bok)
+        return;
+    const double scale = J.qpp[b] * J.wake_scale;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = kb + 4 * g + r;
+        if (k >= nb)
+            continue;
+        double v = 0.0;
+        if (MODE == kWakeFP32) {
+            v = (double)acc[0][r];
+        } else {
+            double w = 1.0;
+            for (int p = 0; p < np; ++p, w *= 256.0)
+                v = fma(w, (double)acc[p][r], v);
+        }
+        J.V[(size_t)b * nb + k] = scale * v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -635,9 +790,11 @@ static hipError_t push_n(const PushLaunch &l, bool push, hipStream_t s)
 {
     const size_t lds = push_lds_bytes(l.nbins_max, l.nsub_max);
     if (push)
-        hipLaunchKernelGGL((k_push<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s, l);
+        hipLaunchKernelGGL((k_push<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s, l.jobs,
+                           l.items, l.nitems, l.grid);
     else
-        hipLaunchKernelGGL((k_push<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s, l);
+        hipLaunchKernelGGL((k_push<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s, l.jobs,
+                           l.items, l.nitems, l.grid);
     return hipGetLastError();
 }
 
@@ -678,6 +835,27 @@ hipError_t launch_scan(const ScanLaunch &l, hipStream_t s)
     if (l.njobs < 1)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_scan, dim3(l.njobs), dim3(kPrepThreads), 0, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_wake(const WakeLaunch &l, hipStream_t s)
+{
+    if (l.nitems < 1 || l.nbins_max < 1)
+        return hipErrorInvalidValue;
+    const int kmax = std::min(l.nbins_max, 4096);
+    switch (l.mode) {
+    case kWakeFP32:
+        hipLaunchKernelGGL((k_wake<kWakeFP32>), dim3(l.nitems), dim3(256), (size_t)kmax * 4, s, l);
+        break;
+    case kWakeBF16x2:
+        hipLaunchKernelGGL((k_wake<kWakeBF16x2>), dim3(l.nitems), dim3(256), (size_t)kmax * 4, s, l);
+        break;
+    case kWakeBF16x3:
+        hipLaunchKernelGGL((k_wake<kWakeBF16x3>), dim3(l.nitems), dim3(256), (size_t)kmax * 6 + 8, s, l);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

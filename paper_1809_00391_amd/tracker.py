@@ -203,6 +203,14 @@ class Tracker:
         self._check(self._L.mbt_wake_potential(self._h, C.c_void_p(V.ctypes.data)))
         return V
 
+    WAKE_MODES = {"fp64": _abi.MBT_WAKE_FP64, "fp32": _abi.MBT_WAKE_FP32,
+                  "bf16x2": _abi.MBT_WAKE_BF16X2, "bf16x3": _abi.MBT_WAKE_BF16X3}
+
+    def set_wake_precision(self, mode):
+        """Arithmetic of the short-range wake potential: "fp64" (default),
+        "fp32", "bf16x2" or "bf16x3" (matrix cores)."""
+        self._check(self._L.mbt_set_wake_precision(self._h, self.WAKE_MODES[mode]))
+
     def set_launch(self, nsub=0, push_grid=0):
         """Push launch shape (sub-histograms, persistent workgroups; 0: defaults)."""
         self._check(self._L.mbt_set_launch(self._h, int(nsub), int(push_grid)))
