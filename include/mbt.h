@@ -100,6 +100,15 @@ typedef struct {
     double tau_max_s;   /* > tau_min_s                                        */
 } mbt_grid;
 
+/* Round resistive pipe for the short-range resistive-wall wake (the wake
+ * benchmark of Sec. 3: a copper chamber of 10 mm radius along the whole
+ * ring). */
+typedef struct {
+    double radius_m;         /* b > 0                                         */
+    double conductivity_S_m; /* DC conductivity > 0 (copper 5.8e7)            */
+    double length_m;         /* pipe length > 0 (e.g. the circumference)      */
+} mbt_resistive_wall;
+
 /* Per-bunch statistics after a turn (Sec. 2.4): means and population rms
  * over all macro-particles of the bunch. */
 typedef struct {
@@ -157,6 +166,15 @@ int mbt_set_fill(mbt_ctx *ctx, int32_t M, const int32_t *bucket, const double *c
  * Must precede mbt_bind. */
 int mbt_set_short_range(mbt_ctx *ctx, int32_t nres, const mbt_resonator *res,
                         const mbt_grid *g);
+
+/* Short-range resistive-wall wake of a round pipe added to the wake table
+ * (rw == NULL removes it): with z = c t and s0 = (2 b^2 / (Z0 sigma))^(1/3),
+ * W = (4 Z0 c L / (pi b^2)) [exp(-z/s0) cos(sqrt(3) z/s0)/3 - (sqrt(2)/pi)
+ * int_0^inf x^2 exp(-x^2 z/s0)/(x^6 + 8) dx] (Bane and Sands, 1995), sampled
+ * at bin distances like the resonators (W(0+)/2 for the bin itself).  Acts
+ * only with a grid.  MBT_EINVAL on a non-positive or non-finite value.
+ * Must precede mbt_bind. */
+int mbt_set_resistive_wall(mbt_ctx *ctx, const mbt_resistive_wall *rw);
 
 /* Long-range resonators (Sec. 4 higher-order mode): each acts on later
  * bunch passages through a complex phasor rotated bucket to bucket; its

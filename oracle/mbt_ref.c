@@ -103,6 +103,59 @@ double mbt_ref_resonator_wake(const mbt_ref_resonator *r, double t)
            (cos(wbar * t) - (alpha / wbar) * sin(wbar * t));
 }
 
+/* x^2 exp(-a x^2) / (x^6 + 8) integrated over [0, inf): for a >= 1 after
+ * x = s / sqrt(a) over s in [0, 7] (the rest is below 1e-20 of the total);
+ * for a < 1 as [0, 1] in x plus [0, 1] in y = 1/x.  Composite Simpson with
+ * 2n and n intervals combined by one Richardson step (Boole's rule). */
+static double rw_f_large(double s, double a)
+{
+    return s * s * exp(-s * s) / (8.0 + s * s * s * s * s * s / (a * a * a));
+}
+static double rw_f_x(double x, double a) { return x * x * exp(-a * x * x) / (x * x * x * x * x * x + 8.0); }
+static double rw_f_y(double y, double a)
+{
+    if (y == 0.0)
+        return 0.0;
+    return y * y * exp(-a / (y * y)) / (1.0 + 8.0 * y * y * y * y * y * y);
+}
+static double simpson(double (*f)(double, double), double a, double lo, double hi, int n)
+{
+    double h = (hi - lo) / n, sum = f(lo, a) + f(hi, a);
+    for (int i = 1; i < n; ++i)
+        sum += (i & 1 ? 4.0 : 2.0) * f(lo + i * h, a);
+    return sum * h / 3.0;
+}
+static double boole(double (*f)(double, double), double a, double lo, double hi)
+{
+    const int n = 20000;
+    double s2 = simpson(f, a, lo, hi, 2 * n), s1 = simpson(f, a, lo, hi, n);
+    return s2 + (s2 - s1) / 15.0;
+}
+static double rw_integral(double a)
+{
+    if (a >= 1.0)
+        return boole(rw_f_large, a, 0.0, 7.0) / (a * sqrt(a));
+    return boole(rw_f_x, a, 0.0, 1.0) + boole(rw_f_y, a, 0.0, 1.0);
+}
+
+double mbt_ref_rw_wake(const mbt_ref_rw *rw, double t)
+{
+    if (t < 0.0)
+        return 0.0;
+    const double c = 299792458.0, z0 = 376.730313668;
+    const double b = rw->radius_m;
+    const double s0 = cbrt(2.0 * b * b / (z0 * rw->conductivity_S_m));
+    const double u = c * t / s0;
+    const double amp = 4.0 * z0 * c * rw->length_m / (PI * b * b);
+    return amp * (exp(-u) * cos(sqrt(3.0) * u) / 3.0 - (sqrt(2.0) / PI) * rw_integral(u));
+}
+
+static int rw_ok(const mbt_ref_rw *rw)
+{
+    return rw && isfinite(rw->radius_m) && rw->radius_m > 0.0 && isfinite(rw->conductivity_S_m) &&
+           rw->conductivity_S_m > 0.0 && isfinite(rw->length_m) && rw->length_m > 0.0;
+}
+
 static int grid_ok(const mbt_ref_grid *g)
 {
     return g && g->nbins >= 1 && g->nbins <= 4096 && isfinite(g->tau_min_s) &&
@@ -134,6 +187,21 @@ int mbt_ref_wake_table(int32_t nres, const mbt_ref_resonator *res, const mbt_ref
         for (int32_t k = 1; k < g->nbins; ++k)
             W[k] += mbt_ref_resonator_wake(&res[i], (double)k * delta_t);
     }
+    return MBT_REF_OK;
+}
+
+int mbt_ref_wake_table_rw(int32_t nres, const mbt_ref_resonator *res, const mbt_ref_rw *rw,
+                          const mbt_ref_grid *g, double *W)
+{
+    int rc = mbt_ref_wake_table(nres, res, g, W);
+    if (rc || !rw)
+        return rc;
+    if (!rw_ok(rw))
+        return MBT_REF_EINVAL;
+    double delta_t = (g->tau_max_s - g->tau_min_s) / (double)g->nbins;
+    W[0] += 0.5 * mbt_ref_rw_wake(rw, 0.0);
+    for (int32_t k = 1; k < g->nbins; ++k)
+        W[k] += mbt_ref_rw_wake(rw, (double)k * delta_t);
     return MBT_REF_OK;
 }
 
@@ -240,6 +308,8 @@ struct mbt_ref_sim {
     mbt_ref_grid grid;
     int32_t n_sr;
     mbt_ref_resonator sr[MAX_RES];
+    int rw_on;
+    mbt_ref_rw rw;
     double *W; /* rebuilt by prepare() */
     /* long-range resonators */
     int32_t n_lr;
@@ -461,6 +531,19 @@ int mbt_ref_set_long_range(mbt_ref_sim *s, int32_t nres, const mbt_ref_resonator
     return MBT_REF_OK;
 }
 
+int mbt_ref_set_resistive_wall(mbt_ref_sim *s, const mbt_ref_rw *rw)
+{
+    if (!s)
+        return MBT_REF_EINVAL;
+    if (rw && !rw_ok(rw))
+        return fail(s, MBT_REF_EINVAL, "resistive wall: need radius, conductivity, length > 0");
+    s->rw_on = rw != NULL;
+    if (rw)
+        s->rw = *rw;
+    s->prepared = 0;
+    return MBT_REF_OK;
+}
+
 /* Build the wake table (short-range resonators plus the long-range ones, whose
  * same-bunch same-turn part acts through the bins) and the gap rotations. */
 static int prepare(mbt_ref_sim *s)
@@ -481,7 +564,7 @@ static int prepare(mbt_ref_sim *s)
         s->W = malloc(sizeof(double) * (size_t)s->grid.nbins);
         if (!s->W)
             return fail(s, MBT_REF_ENOMEM, "out of memory");
-        int rc = mbt_ref_wake_table(n, all, &s->grid, s->W);
+        int rc = mbt_ref_wake_table_rw(n, all, s->rw_on ? &s->rw : NULL, &s->grid, s->W);
         if (rc)
             return fail(s, rc, "wake table");
     }

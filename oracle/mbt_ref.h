@@ -66,6 +66,14 @@ typedef struct {
     double tau_max_s;
 } mbt_ref_grid;
 
+/* Round resistive pipe: radius b, DC conductivity, length (the paper's
+ * validation used a copper chamber of 10 mm radius around the whole ring). */
+typedef struct {
+    double radius_m;
+    double conductivity_S_m;
+    double length_m;
+} mbt_ref_rw;
+
 typedef struct mbt_ref_sim mbt_ref_sim;
 
 /* ---- free functions (also used as pins) ---------------------------------- */
@@ -79,6 +87,19 @@ void mbt_ref_normal_pair(uint64_t seed, const uint32_t c[4], double z[2]);
 
 /* Resonator wake W(t) in V/C for t > 0 (0 for t < 0; W(0+) at t == 0). */
 double mbt_ref_resonator_wake(const mbt_ref_resonator *r, double t);
+
+/* Short-range resistive-wall wake of a round pipe in V/C (Bane and Sands,
+ * 1995): with z = c t, s0 = (2 b^2 / (Z0 sigma))^(1/3),
+ *   W = (4 Z0 c L / (pi b^2)) [ exp(-z/s0) cos(sqrt(3) z/s0) / 3
+ *        - (sqrt(2)/pi) int_0^inf x^2 exp(-x^2 z/s0) / (x^6 + 8) dx ],
+ * so W(0+) = Z0 c L / (pi b^2).  0 for t < 0.  Parity unpinned beyond the
+ * tests' closed-form limits and impedance transform. */
+double mbt_ref_rw_wake(const mbt_ref_rw *rw, double t);
+
+/* Wake table on a grid: W[0] = sum W(0+)/2, W[k] = sum W(k*Delta), over the
+ * resonators and the resistive wall (rw may be NULL). */
+int mbt_ref_wake_table_rw(int32_t nres, const mbt_ref_resonator *res, const mbt_ref_rw *rw,
+                          const mbt_ref_grid *g, double *W);
 
 /* Wake table on a grid: W[0] = sum W(0+)/2, W[k] = sum W(k*Delta). */
 int mbt_ref_wake_table(int32_t nres, const mbt_ref_resonator *res,
@@ -113,6 +134,9 @@ int mbt_ref_set_fill(mbt_ref_sim *s, int32_t M, const int32_t *bucket,
 int mbt_ref_set_short_range(mbt_ref_sim *s, int32_t nres, const mbt_ref_resonator *res,
                             const mbt_ref_grid *g /* NULL = no short-range kick */);
 int mbt_ref_set_long_range(mbt_ref_sim *s, int32_t nres, const mbt_ref_resonator *res);
+/* Resistive wall added to the short-range table (acts only with a grid);
+ * NULL removes it. */
+int mbt_ref_set_resistive_wall(mbt_ref_sim *s, const mbt_ref_rw *rw);
 
 int mbt_ref_init_gaussian(mbt_ref_sim *s, int64_t N, double sigma_tau_s,
                           double sigma_delta, uint64_t seed);

@@ -32,6 +32,11 @@ class RefGrid(C.Structure):
     _fields_ = [("nbins", C.c_int32), ("tau_min_s", C.c_double), ("tau_max_s", C.c_double)]
 
 
+class RefRW(C.Structure):
+    _fields_ = [("radius_m", C.c_double), ("conductivity_S_m", C.c_double),
+                ("length_m", C.c_double)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -45,6 +50,9 @@ def lib():
             "mbt_ref_normal_pair": (None, [C.c_uint64, up, dp]),
             "mbt_ref_resonator_wake": (C.c_double, [P(RefResonator), C.c_double]),
             "mbt_ref_wake_table": (C.c_int, [C.c_int32, P(RefResonator), P(RefGrid), dp]),
+            "mbt_ref_rw_wake": (C.c_double, [P(RefRW), C.c_double]),
+            "mbt_ref_wake_table_rw": (C.c_int, [C.c_int32, P(RefResonator), P(RefRW), P(RefGrid), dp]),
+            "mbt_ref_set_resistive_wall": (C.c_int, [sims, P(RefRW)]),
             "mbt_ref_bin_index": (C.c_int32, [P(RefGrid), C.c_double]),
             "mbt_ref_histogram": (C.c_int, [P(RefGrid), C.c_int64, dp, up, P(C.c_int64)]),
             "mbt_ref_wake_potential": (C.c_int, [C.c_int32, dp, up, C.c_double, dp]),
@@ -114,11 +122,17 @@ def resonator_wake(rs, q, fr, t):
     return lib().mbt_ref_resonator_wake(C.byref(r), float(t))
 
 
-def wake_table(resonators, grid):
+def rw_wake(rw, t):
+    """Short-range resistive-wall wake W(t) in V/C; rw = (radius, conductivity, length)."""
+    return lib().mbt_ref_rw_wake(C.byref(RefRW(*map(float, rw))), float(t))
+
+
+def wake_table(resonators, grid, rw=None):
     arr = (RefResonator * max(1, len(resonators)))(*[RefResonator(*r) for r in resonators])
     g = RefGrid(*grid)
     W = np.zeros(g.nbins)
-    rc = lib().mbt_ref_wake_table(len(resonators), arr, C.byref(g), _dp(W))
+    r = None if rw is None else C.byref(RefRW(*map(float, rw)))
+    rc = lib().mbt_ref_wake_table_rw(len(resonators), arr, r, C.byref(g), _dp(W))
     if rc:
         raise OracleError(rc, "wake_table")
     return W
@@ -217,6 +231,10 @@ class RefSim:
         arr = (RefResonator * max(1, len(resonators)))(*[RefResonator(*r) for r in resonators])
         self._check(lib().mbt_ref_set_long_range(self._h, len(resonators), arr))
         self.n_lr = len(resonators)
+
+    def set_resistive_wall(self, rw):
+        r = None if rw is None else C.byref(RefRW(*map(float, rw)))
+        self._check(lib().mbt_ref_set_resistive_wall(self._h, r))
 
     def init_gaussian(self, N, sigma_tau, sigma_delta, seed):
         self._check(lib().mbt_ref_init_gaussian(self._h, N, sigma_tau, sigma_delta, seed))

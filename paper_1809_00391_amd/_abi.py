@@ -46,6 +46,11 @@ class Grid(C.Structure):
     _fields_ = [("nbins", C.c_int32), ("tau_min_s", C.c_double), ("tau_max_s", C.c_double)]
 
 
+class ResistiveWall(C.Structure):
+    _fields_ = [("radius_m", C.c_double), ("conductivity_S_m", C.c_double),
+                ("length_m", C.c_double)]
+
+
 class Moments(C.Structure):
     _fields_ = [("mean_tau", C.c_double), ("mean_delta", C.c_double),
                 ("rms_tau", C.c_double), ("rms_delta", C.c_double)]
@@ -63,6 +68,7 @@ SIGNATURES = {
     "mbt_set_fill": (C.c_int, [_ctx, C.c_int32, _P(C.c_int32), _P(C.c_double), _P(C.c_int32)]),
     "mbt_set_short_range": (C.c_int, [_ctx, C.c_int32, _P(Resonator), _P(Grid)]),
     "mbt_set_long_range": (C.c_int, [_ctx, C.c_int32, _P(Resonator)]),
+    "mbt_set_resistive_wall": (C.c_int, [_ctx, _P(ResistiveWall)]),
     "mbt_query_bytes": (C.c_int, [_ctx, C.c_int64, _P(C.c_size_t), _P(C.c_size_t)]),
     "mbt_bind": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
                            C.c_void_p]),

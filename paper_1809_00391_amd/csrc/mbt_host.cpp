@@ -6,6 +6,7 @@
 // device rings that are copied to pinned host memory chunk by chunk.
 #include "mbt.h"
 #include "mbt_internal.h"
+#include "mbt_rw.h"
 
 #include <hip/hip_runtime.h>
 
@@ -196,6 +197,8 @@ struct mbt_ctx {
     bool sr_on = false;
     mbt_grid grid{};
     std::vector<Resonator> sr, lr;
+    bool rw_on = false;
+    ResistiveWall rw{};
     // binding
     bool bound = false;
     int64_t N = 0;
@@ -853,6 +856,22 @@ int mbt_set_long_range(mbt_ctx *c, int32_t nres, const mbt_resonator *res)
     return MBT_OK;
 }
 
+int mbt_set_resistive_wall(mbt_ctx *c, const mbt_resistive_wall *rw)
+{
+    if (!c)
+        return MBT_EINVAL;
+    if (c->bound)
+        return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
+    if (rw && !(std::isfinite(rw->radius_m) && rw->radius_m > 0.0 &&
+                std::isfinite(rw->conductivity_S_m) && rw->conductivity_S_m > 0.0 &&
+                std::isfinite(rw->length_m) && rw->length_m > 0.0))
+        return fail(c, MBT_EINVAL, "resistive wall: need radius, conductivity and length > 0");
+    c->rw_on = rw != nullptr;
+    if (rw)
+        c->rw = ResistiveWall{rw->radius_m, rw->conductivity_S_m, rw->length_m};
+    return MBT_OK;
+}
+
 int mbt_query_bytes(const mbt_ctx *c, int64_t N, size_t *state_bytes, size_t *work_bytes)
 {
     if (!c || !state_bytes || !work_bytes)
@@ -903,6 +922,13 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
             W[0] += 0.5 * r.wake(0.0);
             for (int k = 1; k < nb; ++k)
                 W[k] += r.wake((double)k * dt);
+        }
+        if (c->rw_on) {
+            std::vector<double> gx, gw;
+            gauss_legendre(24, gx, gw);
+            W[0] += 0.5 * rw_wake(c->rw, 0.0, gx, gw);
+            for (int k = 1; k < nb; ++k)
+                W[k] += rw_wake(c->rw, (double)k * dt, gx, gw);
         }
     }
     std::vector<double> qpp(M), gap((size_t)std::max(nlr, 1) * M * 2, 0.0),

@@ -61,6 +61,8 @@ def make_job(w, wake="fp64"):
         t.set_short_range(list(w.short_range), w.grid)
     if w.long_range:
         t.set_long_range(list(w.long_range))
+    if w.rw is not None:
+        t.set_resistive_wall(w.rw)
     if wake != "fp64" and w.grid is not None:
         t.set_wake_precision(wake)
     t.bind(w.N)

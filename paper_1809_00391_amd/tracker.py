@@ -124,6 +124,14 @@ class Tracker:
         self._check(self._L.mbt_set_long_range(self._h, n, arr))
         self.n_lr = n
 
+    def set_resistive_wall(self, rw):
+        """Short-range resistive wall (radius m, conductivity S/m, length m), or None."""
+        if rw is None:
+            self._check(self._L.mbt_set_resistive_wall(self._h, None))
+        else:
+            r = _abi.ResistiveWall(*map(float, rw))
+            self._check(self._L.mbt_set_resistive_wall(self._h, C.byref(r)))
+
     def query_bytes(self, N):
         sb, wb = C.c_size_t(), C.c_size_t()
         self._check(self._L.mbt_query_bytes(self._h, int(N), C.byref(sb), C.byref(wb)))

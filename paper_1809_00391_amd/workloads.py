@@ -44,6 +44,7 @@ class Workload:
     long_range: tuple = ()
     hc_flat: tuple = None  # (n, fraction of the flat-potential voltage)
     streams: tuple = None
+    rw: tuple = None       # resistive wall (radius m, conductivity S/m, length m)
     notes: str = field(default="", compare=False)
 
     @property
@@ -99,6 +100,9 @@ C4 = Workload(
     ring=RING_R484, buckets=tuple(range(484)), currents_A=(1e-3,) * 484, N=100_000,
     turns=20_000, seed=4, sigma_tau0=10e-12, sigma_delta0=8.6e-4, short_range=(BB,),
     grid=(256, -76.15e-12, 76.15e-12), long_range=(HOM,))
+
+# The paper's wake validation: copper chamber, 10 mm radius, whole ring.
+RW_COPPER_10MM = (0.010, 5.8e7, 288.0)
 
 PRESETS = {"c1": C1, "c2": C2, "c3": C3, "c4": C4}
 

@@ -24,6 +24,8 @@ def make_oracle(w, N=None, init=True, hc_override=None):
         s.set_short_range(list(w.short_range), w.grid)
     if w.long_range:
         s.set_long_range(list(w.long_range))
+    if w.rw is not None:
+        s.set_resistive_wall(w.rw)
     n = N or w.N
     if init:
         s.init_gaussian(n, w.sigma_tau0, w.sigma_delta0, w.seed)
@@ -43,6 +45,8 @@ def make_tracker(w, N=None, init=True, hc_override=None):
         t.set_short_range(list(w.short_range), w.grid)
     if w.long_range:
         t.set_long_range(list(w.long_range))
+    if w.rw is not None:
+        t.set_resistive_wall(w.rw)
     n = N or w.N
     t.bind(n)
     if init:

@@ -192,3 +192,31 @@ def test_parity_more_cases(cuda, case):
         assert np.max(np.abs(mg[..., :2] - mo[..., :2]) / scale) <= MOMENT_RTOL
     if w.long_range:
         assert np.allclose(g.get_state()[2], o.get_state()[2], rtol=1e-9, atol=0)
+
+
+# The paper's wake benchmark: the short-range resistive wall of a copper pipe
+# of 10 mm radius around the whole ring, on a negative-momentum-compaction
+# lattice, single bunch at several mA.
+RW_CASE = wl.C1.with_(name="resistive wall", ring=dict(wl.RING_R480, alpha_c=-6e-4),
+                      currents_A=(5e-3,), short_range=(), rw=wl.RW_COPPER_10MM, N=20_000,
+                      grid=(128, -60e-12, 60e-12))
+
+
+def test_resistive_wall_parity(cuda):
+    w = RW_CASE
+    print_case("resistive wall", N=w.N)
+    o = make_oracle(w, init=False)
+    g = make_tracker(w, init=False)
+    W_o = ref.wake_table([], w.grid, rw=w.rw)
+    W_g = g.wake_table()
+    # two independent quadratures of the same integral
+    assert np.max(np.abs(W_g - W_o)) <= 1e-13 * np.max(np.abs(W_o))
+    set_same_particles(w, [o, g], w.N)
+    o.track(1)
+    g.track(1)
+    to, do = o.get_particles(0)
+    tg, dg = g.get_particles(0)
+    assert coord_excess(tg, to) <= COORD_RTOL and coord_excess(dg, do) <= COORD_RTOL
+    mo = o.track(100)
+    mg = g.track(100)
+    assert moment_excess(mg, mo) <= MOMENT_RTOL

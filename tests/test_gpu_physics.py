@@ -93,3 +93,32 @@ def test_coupled_bunch_growth_sacherer(cuda):
     g_eq7 = th.cb_growth_frequency_domain(ring, wl.HOM, 0.1e-3, 480, 19)
     g = _cb_growth(ring, 0.1e-3, 19, 12000)
     assert g == pytest.approx(g_eq7, rel=2e-2), (g, g_eq7)
+
+
+def test_passive_harmonic_cavity_beam_loading(cuda):
+    """Passive third-harmonic cavity (a long-range resonator near 3 f_RF) in a
+    uniform fill: the steady-state beam-induced voltage at a bunch equals
+    2 I0 sum_p Re Z(p w_b) (Poisson summation over the train), 1e-9."""
+    ring = dict(R480, alpha_c=1e-12, sigma_delta=0.0)
+    h, f_rf = ring["harmonic"], ring["f_rf_Hz"]
+    T_rf = 1.0 / f_rf
+    I_b, rs, Q = 0.4e-3, 2.0e3, 2.0e4
+    fr = 3 * f_rf + 0.1e6
+    q = I_b * T0
+    w = wl.Workload(name="passive hc", ring=ring, buckets=tuple(range(h)), currents_A=(I_b,) * h,
+                    N=1, turns=300, seed=1, sigma_tau0=0.0, sigma_delta0=0.0,
+                    long_range=((rs, Q, fr),))
+    g = make_tracker(w, init=False)
+    for b in range(h):
+        g.set_particles(b, [0.0], [0.0])
+    g.track(300)
+    ph = g.get_state()[2]
+    wr = 2 * np.pi * fr
+    a = wr / (2 * Q)
+    wb = np.sqrt(wr * wr - a * a)
+    got = (np.exp((-a + 1j * wb) * T_rf) * complex(ph[0], ph[1])).real + q * a * rs
+    P = 2_000_000
+    p = np.arange(1, P + 1, dtype=float)
+    reZ = th.resonator_impedance(rs, Q, fr, p * 2 * np.pi * f_rf).real
+    want = 2 * (q / T_rf) * (np.sum(reZ) + rs * (fr / f_rf) ** 2 / (Q * Q * P))
+    assert got == pytest.approx(want, rel=1e-9)

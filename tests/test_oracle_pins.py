@@ -387,6 +387,51 @@ def test_long_range_matches_brute_force():
     assert np.max(np.abs(free[:, 1, :] - bf[1])) > 1e-6 * 8e-4
 
 
+def test_passive_harmonic_cavity_beam_loading():
+    """A passive harmonic cavity is a high-Q long-range resonator near n f_RF
+    driven only by the beam.  For a uniform fill of point bunches (charge q,
+    spacing T_rf, current I0 = q / T_rf) its steady-state voltage at a bunch,
+    counting the bunch's own half charge (W(0+)/2 = alpha Rs per unit charge),
+    is by Poisson summation over the bunch train 2 I0 sum_{p>=1} Re Z(p w_b)
+    (Z(0) = 0 for a resonator).  The oracle gets it by rotating and depositing
+    into one phasor bucket by bucket; the frequency-domain sum is independent
+    of that recursion.  Particles are held at tau = 0 by a vanishing momentum
+    compaction."""
+    ring = dict(R480, alpha_c=1e-12, sigma_delta=0.0)
+    h = ring["harmonic"]
+    f_rf = ring["f_rf_Hz"]
+    T_rf = 1.0 / f_rf
+    I_b = 0.4e-3
+    q = I_b * T0
+    rs, Q = 2.0e3, 2.0e4
+    fr = 3 * f_rf + 0.1e6               # third harmonic, detuned by 100 kHz
+    s = ref.RefSim(ring)
+    s.set_fill(list(range(h)), [I_b] * h)
+    s.set_long_range([(rs, Q, fr)])
+    s.alloc_particles(1, 1)
+    for b in range(h):
+        s.set_particles(b, [0.0], [0.0])
+    s.track(300)                         # the fill time is a few turns
+    _, _, ph = s.get_state()
+    V = complex(ph[0], ph[1])            # just after the last bunch's deposit
+    wr = 2 * np.pi * fr
+    a = wr / (2 * Q)
+    wb = np.sqrt(wr * wr - a * a)
+    seen = (np.exp((-a + 1j * wb) * T_rf) * V).real   # at the next bucket
+    got = seen + q * a * rs
+    I0 = q / T_rf
+    P = 2_000_000
+    p = np.arange(1, P + 1, dtype=float)
+    w = p * 2 * np.pi * f_rf
+    reZ = th.resonator_impedance(rs, Q, fr, w).real
+    tail = rs * (fr / f_rf) ** 2 / (Q * Q * P)       # sum over p > P of Rs / (Q p / n)^2
+    want = 2 * I0 * (np.sum(reZ) + tail)
+    assert got == pytest.approx(want, rel=1e-9)
+    # the detuned cavity's fundamental term dominates: Rs cos^2(psi)
+    tan_psi = Q * (3 * f_rf / fr - fr / (3 * f_rf))
+    assert want == pytest.approx(2 * I0 * rs / (1 + tan_psi ** 2), rel=1e-3)
+
+
 def _cb_oracle_growth(ring, M, mu, current, turns, res=wl.HOM, A=1e-13):
     """Seed the single mode z_b = tau_b - i (alpha_c/omega_s) delta_b =
     A exp(2 pi i mu b / M) and fit the growth of its amplitude."""
@@ -495,3 +540,75 @@ def test_validation_errors():
         s.track(1)  # no fill, no particles
     with pytest.raises(ref.OracleError):
         s.set_harmonic_cavity({"n": 3, "v_ratio": 10.0, "phase_n_rad": -1.5})
+
+
+# ---------------------------------------------------------------------------
+# Short-range resistive-wall wake (the paper's validation: copper, 10 mm)
+# ---------------------------------------------------------------------------
+
+RW_CU = (0.010, 5.8e7, 288.0)     # radius m, conductivity S/m, length m
+C_LIGHT, Z0 = 299792458.0, 376.730313668
+
+
+def test_resistive_wall_wake_limits():
+    """W(0+) = Z0 c L / (pi b^2), independent of the conductivity; far behind
+    the charge the classic thick-wall wake -(c L / (4 pi b)) sqrt(Z0 / (pi
+    sigma)) z^-3/2, which follows from the thick-wall impedance alone."""
+    b, sig, L = RW_CU
+    assert ref.rw_wake(RW_CU, 0.0) == pytest.approx(Z0 * C_LIGHT * L / (np.pi * b * b), rel=1e-13)
+    assert ref.rw_wake((b, 10 * sig, L), 0.0) == pytest.approx(ref.rw_wake(RW_CU, 0.0), rel=1e-13)
+    s0 = (2 * b * b / (Z0 * sig)) ** (1 / 3)
+    for u in (1e3, 1e4):
+        z = u * s0
+        classic = -(C_LIGHT * L / (4 * np.pi * b)) * np.sqrt(Z0 / (np.pi * sig)) * z ** -1.5
+        assert ref.rw_wake(RW_CU, z / C_LIGHT) == pytest.approx(classic, rel=3.0 / u ** 3 + 1e-11)
+    assert ref.rw_wake(RW_CU, -1e-12) == 0.0
+
+
+@pytest.mark.parametrize("kappa", [0.2, 1.0, 3.0])
+def test_resistive_wall_wake_transforms_to_impedance(kappa):
+    """The Fourier transform of the wake is the round-pipe impedance with DC
+    conductivity, Z(w) = (L / (2 pi b)) / (1/Z_s + i w eps0 b / 2) with the
+    surface impedance Z_s = (1 + i) sqrt(w mu0 / (2 sigma)), at w = kappa c/s0
+    where the short-range term matters."""
+    import warnings
+    b, sig, L = RW_CU
+    s0 = (2 * b * b / (Z0 * sig)) ** (1 / 3)
+    W = lambda u: ref.rw_wake(RW_CU, u * s0 / C_LIGHT)
+    U = 60.0
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", integrate.IntegrationWarning)
+        re = integrate.quad(lambda u: W(u) * np.cos(kappa * u), 0, U, limit=400, epsabs=0,
+                            epsrel=1e-11)[0]
+        im = -integrate.quad(lambda u: W(u) * np.sin(kappa * u), 0, U, limit=400, epsabs=0,
+                             epsrel=1e-11)[0]
+        re += integrate.quad(W, U, np.inf, weight="cos", wvar=kappa, limlst=200)[0]
+        im -= integrate.quad(W, U, np.inf, weight="sin", wvar=kappa, limlst=200)[0]
+    z_num = (s0 / C_LIGHT) * complex(re, im)
+    w = kappa * C_LIGHT / s0
+    zs = (1 + 1j) * np.sqrt(w * (Z0 / C_LIGHT) / (2 * sig))
+    z_th = (L / (2 * np.pi * b)) / (1 / zs + 1j * w * b / (2 * Z0 * C_LIGHT))
+    assert abs(z_num - z_th) <= 1e-9 * abs(z_th)
+
+
+def test_resistive_wall_table_and_tracking_hook():
+    """The table adds the wall's samples (self term W(0+)/2) to the
+    resonators', and a simulation with the wall set kicks differently from
+    one without."""
+    grid = (128, -60e-12, 60e-12)
+    W_res = ref.wake_table([wl.BB], grid)
+    W_all = ref.wake_table([wl.BB], grid, rw=RW_CU)
+    dt = 120e-12 / 128
+    assert W_all[0] - W_res[0] == pytest.approx(0.5 * ref.rw_wake(RW_CU, 0.0), rel=1e-14)
+    k = np.arange(1, 128)
+    extra = np.array([ref.rw_wake(RW_CU, kk * dt) for kk in k])
+    assert np.allclose(W_all[1:] - W_res[1:], extra, rtol=1e-12, atol=1e-12 * np.max(np.abs(extra)))
+    moms = []
+    for rw in (None, RW_CU):
+        s = ref.RefSim(R480)
+        s.set_fill([0], [5e-3])
+        s.set_short_range([wl.BB], grid)
+        s.set_resistive_wall(rw)
+        s.init_gaussian(2000, 10e-12, 8.6e-4, 3)
+        moms.append(s.track(20))
+    assert not np.allclose(moms[0], moms[1], rtol=1e-6, atol=0)
