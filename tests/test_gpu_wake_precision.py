@@ -95,28 +95,31 @@ def test_tracking_error_vs_oracle(cuda):
 
 
 def test_growth_rate_bf16_matches_fp64(cuda):
-    """Coupled-bunch growth with the short-range wake in BF16x2 against the
-    same run in FP64: growth rates agree within 0.1%."""
-    ring = dict(wl.RING_R480, sigma_delta=0.0)
-    M, mu, turns, A = 480, 19, 4000, 1e-13
-    omega_s = 2 * np.pi * th.synchrotron_tune(ring) / (ring["harmonic"] / ring["f_rf_Hz"])
+    """Coupled-bunch growth of a seeded mode in a uniform fill of Gaussian
+    bunches (BB short-range wake on 64 bins, HOM long range, noise and
+    damping on): the growth rate with the wake potential in BF16x2 agrees
+    with the FP64 run of the same seed within 2%."""
+    ring = wl.RING_R480
+    M, mu, turns, A = 480, 19, 3000, 2e-12
     T0 = ring["harmonic"] / ring["f_rf_Hz"]
+    omega_s = 2 * np.pi * th.synchrotron_tune(ring) / T0
     w = wl.Workload(name="cb+bb", ring=ring, buckets=tuple(range(M)), currents_A=(1e-3,) * M,
-                    N=8, turns=turns, seed=1, sigma_tau0=0.0, sigma_delta0=0.0,
-                    short_range=(wl.BB,), grid=(64, -40e-12, 40e-12), long_range=(wl.HOM,))
+                    N=2000, turns=turns, seed=5, sigma_tau0=10e-12, sigma_delta0=8.6e-4,
+                    short_range=(wl.BB,), grid=(64, -60e-12, 60e-12), long_range=(wl.HOM,))
     rates = {}
     for mode in ["fp64", "bf16x2"]:
-        g = make_tracker(w, init=False)
+        g = make_tracker(w)
         if mode != "fp64":
             g.set_wake_precision(mode)
         for b in range(M):
+            tau, delta = g.get_particles(b)
             ph = 2 * np.pi * mu * b / M
-            g.set_particles(b, np.full(w.N, A * np.cos(ph)),
-                            np.full(w.N, -A * omega_s / ring["alpha_c"] * np.sin(ph)))
+            g.set_particles(b, tau + A * np.cos(ph), delta - A * omega_s / ring["alpha_c"] * np.sin(ph))
         m = g.track(turns)
         amp = th.mode_amplitudes(m[:, :, 0], m[:, :, 1], ring["alpha_c"], omega_s)[:, mu]
         t = np.arange(turns) * T0
         sel = slice(turns // 5, turns)
         rates[mode] = th.fit_growth(t[sel], amp[sel])
     print(f"[growth rate] fp64 {rates['fp64']:.6g} /s  bf16x2 {rates['bf16x2']:.6g} /s", flush=True)
-    assert rates["bf16x2"] == pytest.approx(rates["fp64"], rel=1e-3)
+    assert rates["fp64"] > 0  # the mode grows (HOM drive above radiation damping)
+    assert rates["bf16x2"] == pytest.approx(rates["fp64"], rel=2e-2)
