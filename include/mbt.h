@@ -306,10 +306,11 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
 void mbt_batch_destroy(mbt_batch *batch);
 const char *mbt_batch_last_error(const mbt_batch *batch);
 
-/* graph_turns > 1: turns are captured once as a HIP graph of that many turns
- * (at most each job's moment ring and profile ring allow) and replayed; the
- * turn counter lives in device memory, so a replay needs no parameter
- * update.  0 or 1: launches are issued turn by turn.  autotune = 1: on the
+/* graph_turns >= 2: turns are captured once as a HIP graph of that many
+ * turns (rounded down to even, and at most what each job's moment ring and
+ * profile ring allow) and replayed; the turn counter lives in device memory,
+ * so a replay needs no parameter update.  0 or 1: launches are issued turn
+ * by turn.  autotune = 1: on the
  * first call with enough turns, the push's sub-histogram count and
  * persistent grid are timed over real turns and the fastest kept, cached per
  * process by (resonator count, bins, item count); these choices change no

@@ -115,7 +115,7 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     L.items_push = take((size_t)M * L.ntiles * sizeof(Item));
     L.items_prep = take((size_t)M * L.nchunks * sizeof(Item));
     L.items_wake = take((size_t)std::max(L.nwake, 1) * sizeof(Item));
-    L.clock = take(sizeof(uint32_t));
+    L.clock = take(2 * sizeof(uint32_t));
     L.status = take(sizeof(uint32_t));
     L.W = take((size_t)nbx * sizeof(double));
     L.Wbf = take((size_t)3 * nbx * sizeof(uint16_t));
@@ -182,7 +182,7 @@ struct Timer {
 // Pinned host image of what the host writes into a job's workspace.
 struct Mirror {
     JobDesc desc;
-    uint32_t clock;
+    uint32_t clock[2];
 };
 
 struct mbt_ctx {
@@ -219,7 +219,7 @@ struct mbt_ctx {
     // run state
     bool have_particles = false;
     bool dirty = true;  // tile sums, histogram and wake potential do not describe the present state
-    int64_t turn = 0;   // turns completed; the device clock holds turn - 1
+    int64_t turn = 0;   // turns completed
     uint64_t seed = 0;
     char err[512] = "";
 
@@ -387,9 +387,10 @@ struct Engine {
     std::vector<WakeGroup> wakes;  // jobs whose wake potential comes from k_wake
 };
 
-PushLaunch push_launch(const Engine &e, const Group &g)
+PushLaunch push_launch(const Engine &e, const Group &g, int phase)
 {
     PushLaunch l{};
+    l.phase = phase;
     l.jobs = e.jobs;
     l.items = e.push_items + g.item0;
     l.nitems = g.nitems;
@@ -400,10 +401,10 @@ PushLaunch push_launch(const Engine &e, const Group &g)
     return l;
 }
 
-hipError_t enqueue_push(const Engine &e, bool push, hipStream_t s)
+hipError_t enqueue_push(const Engine &e, bool push, int phase, hipStream_t s)
 {
     for (const Group &g : e.groups) {
-        hipError_t r = launch_push(push_launch(e, g), push, s);
+        hipError_t r = launch_push(push_launch(e, g, phase), push, s);
         if (r != hipSuccess)
             return r;
     }
@@ -411,9 +412,10 @@ hipError_t enqueue_push(const Engine &e, bool push, hipStream_t s)
 }
 
 // The between-turn work after a push: sums, histograms, wake potential.
-hipError_t enqueue_prep(const Engine &e, hipStream_t s)
+hipError_t enqueue_prep(const Engine &e, int phase, hipStream_t s)
 {
     PrepLaunch l{};
+    l.phase = phase;
     l.jobs = e.jobs;
     l.items = e.prep_items;
     l.nitems = e.nprep;
@@ -425,6 +427,7 @@ hipError_t enqueue_prep(const Engine &e, hipStream_t s)
         if (r != hipSuccess)
             break;
         WakeLaunch w{};
+        w.phase = phase;
         w.jobs = e.jobs;
         w.items = e.wake_items + g.item0;
         w.nitems = g.nitems;
@@ -437,6 +440,8 @@ hipError_t enqueue_prep(const Engine &e, hipStream_t s)
 
 hipError_t enqueue_scan(const Engine &e, hipStream_t s)
 {
+    if (e.nlr_max == 0)
+        return hipSuccess;  // nothing to scan; the prep advances the counters
     ScanLaunch l{};
     l.jobs = e.jobs;
     l.njobs = e.njobs;
@@ -444,9 +449,10 @@ hipError_t enqueue_scan(const Engine &e, hipStream_t s)
     return launch_scan(l, s);
 }
 
-// One turn of every job: phasor scan (advances the clocks), push, prep of the
-// next turn.  With a timer, four events bracket the three parts.
-hipError_t enqueue_turn(const Engine &e, hipStream_t s, Timer *tm)
+// One turn of every job in launch phase `phase`: phasor scan (with long-range
+// resonators), push, prep (+ wake).  With a timer, four events bracket the
+// three parts.
+hipError_t enqueue_turn(const Engine &e, int phase, hipStream_t s, Timer *tm)
 {
     hipEvent_t *ev = nullptr;
     if (tm && tm->n[0] < Timer::kMax)
@@ -458,11 +464,11 @@ hipError_t enqueue_turn(const Engine &e, hipStream_t s, Timer *tm)
         return r;
     if (ev && (r = hipEventRecord(ev[1], s)) != hipSuccess)
         return r;
-    if ((r = enqueue_push(e, true, s)) != hipSuccess)
+    if ((r = enqueue_push(e, true, phase, s)) != hipSuccess)
         return r;
     if (ev && (r = hipEventRecord(ev[2], s)) != hipSuccess)
         return r;
-    if ((r = enqueue_prep(e, s)) != hipSuccess)
+    if ((r = enqueue_prep(e, phase, s)) != hipSuccess)
         return r;
     if (ev && (r = hipEventRecord(ev[3], s)) != hipSuccess)
         return r;
@@ -499,25 +505,32 @@ Engine single_engine(const mbt_ctx *c)
 }
 
 // Start of a call on job c, enqueued on stream s: upload its descriptor
-// (rings count from the present turn), and if the tile sums, histogram and
-// wake potential are stale, set the device clock and rebuild them with a
-// bin-only pass and a prep.
+// (rings count from the present turn) and put the present turn into counter
+// slot 0, where the call's first turn (phase 0) reads it.  If the tile sums,
+// histogram and wake potential are stale, they are rebuilt first by a
+// bin-only pass and a prep in phase 1 with the counter at turn - 1; that
+// prep writes the turn into slot 0 itself.
 int begin_call(mbt_ctx *c, int prof_stride, hipStream_t s)
 {
     c->mirror->desc = job_desc(c, (uint32_t)c->turn, prof_stride);
     HIPCHK(c, hipMemcpyAsync(c->w<JobDesc>(c->L.desc), &c->mirror->desc, sizeof(JobDesc),
                              hipMemcpyHostToDevice, s));
-    if (!c->dirty)
+    uint32_t *clock = c->w<uint32_t>(c->L.clock);
+    if (!c->dirty) {
+        c->mirror->clock[0] = (uint32_t)c->turn;
+        HIPCHK(c, hipMemcpyAsync(clock, &c->mirror->clock[0], sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, s));
         return MBT_OK;
-    c->mirror->clock = (uint32_t)(c->turn - 1);
-    HIPCHK(c, hipMemcpyAsync(c->w<uint32_t>(c->L.clock), &c->mirror->clock, sizeof(uint32_t),
+    }
+    c->mirror->clock[1] = (uint32_t)(c->turn - 1);
+    HIPCHK(c, hipMemcpyAsync(clock + 1, &c->mirror->clock[1], sizeof(uint32_t),
                              hipMemcpyHostToDevice, s));
     const int nbx = std::max(c->nbins(), 1);
     uint32_t *cnt = c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * nbx;
     HIPCHK(c, hipMemsetAsync(cnt, 0, (size_t)c->M * nbx * sizeof(uint32_t), s));
     const Engine e = single_engine(c);
-    HIPCHK(c, enqueue_push(e, false, s));
-    HIPCHK(c, enqueue_prep(e, s));
+    HIPCHK(c, enqueue_push(e, false, 1, s));
+    HIPCHK(c, enqueue_prep(e, 1, s));
     c->dirty = false;
     return MBT_OK;
 }
@@ -1109,7 +1122,7 @@ int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, in
         const bool timed = c->timer.every > 0 && (t % c->timer.every) == 0;
         HIPCHK(c, ring_advance(c->mom, 1, s));
         HIPCHK(c, ring_advance(c->prof, profile_rows(t, 1, stride), s));
-        HIPCHK(c, enqueue_turn(e, s, timed ? &c->timer : nullptr));
+        HIPCHK(c, enqueue_turn(e, (int)(t & 1), s, timed ? &c->timer : nullptr));
     }
     c->turn += nturns;
     HIPCHK(c, ring_flush(c->mom, s));
@@ -1299,7 +1312,7 @@ struct mbt_batch {
     bool autotune = false, tuned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int exec_turns = 0;
+    int exec_turns = 0, exec_phase = 0;  // captured turns and the phase of the first
     char err[512] = "";
 };
 
@@ -1462,16 +1475,17 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
         for (int r = 0; r < reps && !*rc; ++r, ++used) {
             if ((*rc = batch_rings(B, t + used, 1, stride)))
                 break;
+            const int phase = (int)((t + used) & 1);
             hipError_t e = enqueue_scan(B->eng, B->stream);
             for (size_t gi = 0; gi < cand.size() && e == hipSuccess; ++gi) {
                 e = hipEventRecord(ev[2 * gi], B->stream);
                 if (e == hipSuccess)
-                    e = launch_push(push_launch(B->eng, B->eng.groups[gi]), true, B->stream);
+                    e = launch_push(push_launch(B->eng, B->eng.groups[gi], phase), true, B->stream);
                 if (e == hipSuccess)
                     e = hipEventRecord(ev[2 * gi + 1], B->stream);
             }
             if (e == hipSuccess)
-                e = enqueue_prep(B->eng, B->stream);
+                e = enqueue_prep(B->eng, phase, B->stream);
             if (e == hipSuccess)
                 e = hipStreamSynchronize(B->stream);
             for (size_t gi = 0; gi < cand.size() && e == hipSuccess; ++gi) {
@@ -1501,14 +1515,15 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
     return used;
 }
 
-// Capture `turns` turns of the batch as a graph (on the private stream).
-int batch_capture(mbt_batch *B, int turns)
+// Capture `turns` (even) turns of the batch as a graph (on the private
+// stream), the first in launch phase `phase0`.
+int batch_capture(mbt_batch *B, int turns, int phase0)
 {
     drop_graph(B);
     HIPCHK(B, hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < turns && e == hipSuccess; ++k)
-        e = enqueue_turn(B->eng, B->cap, nullptr);
+        e = enqueue_turn(B->eng, (phase0 + k) & 1, B->cap, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(B->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1520,6 +1535,7 @@ int batch_capture(mbt_batch *B, int turns)
     B->graph = g;
     HIPCHK(B, hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     B->exec_turns = turns;
+    B->exec_phase = phase0;
     return MBT_OK;
 }
 
@@ -1750,9 +1766,10 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
         if (st[j])
             G = (int)std::min<int64_t>(G, (int64_t)c->L.prof_slots * st[j]);
     }
-    if (G > 1) {
-        if (B->exec_turns != G)
-            if ((rc = batch_capture(B, G)))
+    G &= ~1;  // an even number of turns leaves the launch phase where it began
+    if (G >= 2 && t + G <= nturns) {
+        if (B->exec_turns != G || B->exec_phase != (int)(t & 1))
+            if ((rc = batch_capture(B, G, (int)(t & 1))))
                 return rc;
         for (; t + G <= nturns; t += G) {
             if ((rc = batch_rings(B, t, G, st.data())))
@@ -1763,7 +1780,7 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
     for (; t < nturns; ++t) {
         if ((rc = batch_rings(B, t, 1, st.data())))
             return rc;
-        HIPCHK(B, enqueue_turn(B->eng, B->stream, nullptr));
+        HIPCHK(B, enqueue_turn(B->eng, (int)(t & 1), B->stream, nullptr));
     }
     for (mbt_ctx *c : B->jobs) {
         c->turn += nturns;

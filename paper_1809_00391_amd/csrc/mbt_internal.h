@@ -46,9 +46,12 @@ struct MapConst {
 };
 
 // Everything a kernel needs about one job, resident in device memory.  The
-// turn counter `clock` holds the index of the last completed turn (turn - 1,
-// modulo 2^32); it is advanced on the device once per turn, so a captured
-// turn replays without parameter updates.
+// turn counter lives on the device in two slots, so a captured run of turns
+// replays without parameter updates: the launches of one turn carry a phase
+// p (alternating 0, 1, 0, ... from the start of a call); during the push of
+// turn n and the prep after it clock[p] reads n (modulo 2^32), and one prep
+// workgroup per job writes n + 1 into clock[1 - p], which no launch of this
+// turn reads.
 struct JobDesc {
     MapConst c;
     double *tau;              // [M][ld]
@@ -83,7 +86,7 @@ struct JobDesc {
     uint32_t *counts;         // [2][M][max(nbins,1)] histograms by turn parity
     uint32_t *prof_ring;      // [prof_slots][M][nbins]
     uint32_t *status;         // bit 0: non-finite moment
-    uint32_t *clock;          // last completed turn (mod 2^32)
+    uint32_t *clock;          // [2] turn counter by launch phase (see below)
 };
 
 // One unit of work: a tile (push) or a wake-potential chunk (prep) of a bunch.
@@ -103,6 +106,7 @@ enum WakeMode {
 
 // Launch descriptors.
 struct PushLaunch {
+    int phase;                // slot of the turn counter this launch reads
     const JobDesc *jobs;
     const Item *items;
     int nitems;
@@ -112,6 +116,7 @@ struct PushLaunch {
     int grid;                 // workgroups; each takes items g, g + grid, ...
 };
 struct PrepLaunch {
+    int phase;
     const JobDesc *jobs;
     const Item *items;        // (job, bunch, chunk)
     int nitems;
@@ -120,6 +125,7 @@ struct PrepLaunch {
     int do_conv;              // 0: moments only (the state at the end of a call)
 };
 struct WakeLaunch {
+    int phase;
     const JobDesc *jobs;
     const Item *items;        // (job, 16-bunch tile, 64-bin tile)
     int nitems;

@@ -1,15 +1,12 @@
 // mbt_kernels.hip -- HIP kernels of the longitudinal multi-bunch tracker for
 // CDNA4 (gfx950).
 //
-// One turn is three launches on the caller's stream, each covering every
-// bunch of every job it is given (jobs are described by device-resident
-// descriptors, work by item lists, and each job's turn counter lives on the
-// device, so a turn can be captured once and replayed):
-//   k_prep  (per bunch, one workgroup per 64 bins): finishes the previous
-//           push's per-bunch sums (moments, Sec. 2.4, and long-range
-//           deposits) and builds each bunch's binned wake potential from its
-//           line density (Sec. 2.3);
-//   k_scan  (one workgroup per job): advances the job's turn counter and its
+// One turn is two launches on the caller's stream (three with long-range
+// resonators, four with a matrix-core wake), each covering every bunch of
+// every job it is given (jobs are described by device-resident descriptors,
+// work by item lists, and each job's turn counter lives on the device, so a
+// turn can be captured once and replayed), in this order:
+//   k_scan  (one workgroup per job, only with long-range resonators): the
 //           long-range phasors through the bunches in bucket order (a scan
 //           of affine maps);
 //   k_push  (tiles of 4096 particles): the single-particle map of every particle
@@ -17,7 +14,12 @@
 //           short-range kick of the particle's bin; long-range kick; Eq. 5
 //           damping and quantum excitation; Eq. 2 drift), then -- on the new
 //           tau, which is exactly the tau the next turn bins -- the LDS
-//           histogram, the long-range deposit sums and the moment sums.
+//           histogram, the long-range deposit sums and the moment sums;
+//   k_prep  (per bunch, one workgroup per 64 bins): finishes the push's
+//           per-bunch sums (moments, Sec. 2.4, and long-range deposits) and
+//           builds each bunch's binned wake potential from its line density
+//           (Sec. 2.3), and writes the job's next turn counter;
+//   k_wake  (matrix-core wake modes only): the wake potential instead.
 // Particle coordinates are FP64 structure-of-arrays rows, one row per bunch;
 // each thread moves pairs of neighbouring particles with 16-byte loads and
 // stores, and one Philox block gives both particles of a pair their noise.
@@ -264,7 +266,7 @@ constexpr int push_min_blocks() { return NLR == 0 ? 4 : 1; }
 template <int NLR, bool PUSH>
 __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
     const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
-    const int grid)
+    const int grid, const int phase)
 {
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
         const int nb = c.nbins, nbx = nb > 0 ? nb : 1;
         const int b = item.bunch;
         const uint32_t tile = item.part;
-        const uint32_t clock = __builtin_amdgcn_readfirstlane(*J.clock);
+        const uint32_t clock = __builtin_amdgcn_readfirstlane(J.clock[phase]);
         const uint32_t turn = clock;  // push of turn n runs with the clock at n
 
         double *Vs = smem;
@@ -394,12 +396,14 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
 }
 
 // ---------------------------------------------------------------------------
-// k_prep: one workgroup per (job, bunch, 64-bin chunk).  With the clock at
-// n - 1 (start of turn n) it finishes the tile sums of the state after turn
-// n - 1 (moments into the ring row of that turn, deposit sums S), records
+// k_prep: one workgroup per (job, bunch, 64-bin chunk).  After the push of
+// turn n (the counter reads n) it finishes the tile sums of the state after
+// turn n (moments into the ring row of that turn, deposit sums S), records
 // that state's histogram on profile turns, builds 64 bins of the wake
-// potential from it, and clears the histogram buffer the push of turn n
-// fills.
+// potential from it, and clears the histogram buffer the push of turn n + 1
+// fills; one workgroup per job then writes n + 1 into the other counter slot.
+// The bin-only prologue is followed by the same prep with the counter at
+// n - 1.
 // ---------------------------------------------------------------------------
 
 // Moments of bunch b from the tile sums of the last push (Sec. 2.4), and
@@ -517,13 +521,9 @@ __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, d
 }
 
 template <int NLR>
-__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
-{
-    extern __shared__ double psm[];
-    const Item item = L.items[blockIdx.x];
-    const JobDesc &J = L.jobs[item.job];
-    const uint32_t clock = *J.clock;
-    if (item.part == 0)
+__device__ __forceinline__ void prep_body(const PrepLaunch &L, const Item &item, const JobDesc &J,
+                                          const uint32_t clock, double *psm)
+{    if (item.part == 0)
         finish_sums<NLR>(J, item.bunch, clock);
     if (L.do_conv && J.c.sr_on) {
         if (J.wake_mode == kWakeFP64) {
@@ -539,7 +539,18 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
     }
 }
 
-// ---------------------------------------------------------------------------
+template <int NLR>
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
+{
+    extern __shared__ double psm[];
+    const Item item = L.items[blockIdx.x];
+    const JobDesc &J = L.jobs[item.job];
+    const uint32_t clock = J.clock[L.phase];
+    prep_body<NLR>(L, item, J, clock, psm);
+    // the next turn's counter, in the slot no launch of this turn reads
+    if (item.bunch == 0 && item.part == 0 && threadIdx.x == 0)
+        J.clock[L.phase ^ 1] = clock + 1u;
+}// ---------------------------------------------------------------------------
 // k_wake: the short-range wake potential of all bunches as one product of
 // the lower-triangular Toeplitz matrix T[k][m] = W[k - m] (Sec. 2.3) with
 // the matrix of line densities C[m][b] (bin m, bunch b), on the matrix
@@ -578,7 +589,7 @@ __global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
     const int b0 = (int)item.bunch * kWakeBunches;
     const int kt = (int)item.part * kWakeBins;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t clock = *J.clock;
+    const uint32_t clock = J.clock[L.phase];
     const uint32_t *cnt = J.counts + (size_t)((clock + 1u) & 1u) * M * nb;
     constexpr int NW = MODE == kWakeFP32 ? 1 : (MODE == kWakeBF16x2 ? 2 : 3);
 
@@ -667,9 +678,8 @@ __global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
 }
 
 // ---------------------------------------------------------------------------
-// k_scan: one workgroup per job.  Advances the job's clock to the turn about
-// to be pushed, then carries its long-range phasors through the bunches in
-// bucket order.  Passing bunch b maps the phasor x to G_b x + D_b (rotation
+// k_scan: one workgroup per job with long-range resonators, before the push.
+// Carries the job's long-range phasors through the bunches in bucket order.  Passing bunch b maps the phasor x to G_b x + D_b (rotation
 // across the gap from the previous filled bucket, then the bunch's deposit
 // D_b = qpp_b c_r S_b); the bunch sees G_b x.  The chain of M affine maps is
 // evaluated as a scan: each thread composes a contiguous run of bunches, a
@@ -694,8 +704,6 @@ __global__ __launch_bounds__(kPrepThreads) void k_scan(const ScanLaunch L)
     __shared__ cplx mA[kPrepThreads], mB[kPrepThreads];  // composed maps
     const JobDesc &J = L.jobs[blockIdx.x];
     const int tid = threadIdx.x;
-    if (tid == 0)
-        *J.clock = *J.clock + 1u;
     const int M = J.M;
     const int run = (M + kPrepThreads - 1) / kPrepThreads;
     const int b_lo = min(tid * run, M), b_hi = min(b_lo + run, M);
@@ -791,10 +799,10 @@ static hipError_t push_n(const PushLaunch &l, bool push, hipStream_t s)
     const size_t lds = push_lds_bytes(l.nbins_max, l.nsub_max);
     if (push)
         hipLaunchKernelGGL((k_push<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s, l.jobs,
-                           l.items, l.nitems, l.grid);
+                           l.items, l.nitems, l.grid, l.phase);
     else
         hipLaunchKernelGGL((k_push<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s, l.jobs,
-                           l.items, l.nitems, l.grid);
+                           l.items, l.nitems, l.grid, l.phase);
     return hipGetLastError();
 }
 
