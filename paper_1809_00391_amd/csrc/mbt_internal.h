@@ -12,7 +12,7 @@ constexpr int kMaxLR = 4;            // long-range resonators
 #define MBT_PUSH_THREADS 256
 #endif
 #ifndef MBT_PAIRS_PER_THREAD
-#define MBT_PAIRS_PER_THREAD 8
+#define MBT_PAIRS_PER_THREAD 16
 #endif
 constexpr int kPushThreads = MBT_PUSH_THREADS;         // wavefronts of 64
 constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // particle pairs per thread per tile

@@ -9,7 +9,7 @@
 //   k_scan  (one workgroup per job, only with long-range resonators): the
 //           long-range phasors through the bunches in bucket order (a scan
 //           of affine maps);
-//   k_push  (tiles of 4096 particles): the single-particle map of every particle
+//   k_push  (tiles of 8192 particles): the single-particle map of every particle
 //           (Sec. 2.2: Eq. 1 kick with RF, harmonic cavity and U0; Eq. 6
 //           short-range kick of the particle's bin; long-range kick; Eq. 5
 //           damping and quantum excitation; Eq. 2 drift), then -- on the new
@@ -118,10 +118,11 @@ __device__ __forceinline__ void rf_phase(double x0, double x1, double &s0, doubl
 // terms in units of E0:
 //   RF:  V_rf sin(phi_s - w tau)/E0 = a cos(w tau) - b sin(w tau)
 //   HC:  k V_rf sin(n phi_h - n w tau)/E0 = a_h cos(n w tau) - b_h sin(n w tau)
-//   wake: the bin's V/E0 (staged in LDS already divided by E0)
+//   wake: vb = the bin's V/E0 (staged in LDS already divided by E0; read
+//         before the noise so that the LDS latency hides behind it)
 //   long range: Re[(V~/E0) exp((-alpha + i wbar) tau)]
 template <int NLR>
-__device__ __forceinline__ void kick_drift(const MapConst &c, const double *Vs,
+__device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
                                            const double (&seen)[NLR > 0 ? NLR : 1][2], double sx,
                                            double cx, double z, double &t, double &d)
 {
@@ -132,11 +133,8 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double *Vs,
         k += fma(c.hc_a, cn, -c.hc_b * sn);
     }
     k -= c.u0_e;
-    if (c.sr_on) {
-        const int kb = bin_of(c, t);
-        if (kb >= 0)
-            k -= Vs[kb];
-    }
+    if (c.sr_on)
+        k -= vb;  // the bin's wake voltage, 0 outside the grid
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
         const double e = exp_small(-c.lr_alpha[r] * t);
@@ -190,9 +188,11 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
     }
 }
 
+// LDS of the push: V/E0 of every bin plus a zero for "outside the grid",
+// the sub-histograms, and the wavefront partial sums.
 size_t push_lds_bytes(int nbins, int nsub)
 {
-    size_t v = (size_t)nbins * sizeof(double);
+    size_t v = (size_t)(nbins + 1) * sizeof(double);
     size_t h = (size_t)nsub * (size_t)nbins * sizeof(uint32_t);
     h = (h + 7) & ~(size_t)7;
     return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
@@ -211,13 +211,20 @@ __device__ __forceinline__ void pair_compute(const MapConst &c, uint32_t key0, u
                                              double &d1, double *acc)
 {
     if (PUSH) {
+        double vb0 = 0.0, vb1 = 0.0;
+        if (c.sr_on) {
+            const int nb = c.nbins;
+            const int k0 = bin_of(c, t0), k1 = bin_of(c, t1);
+            vb0 = Vs[k0 >= 0 ? k0 : nb];
+            vb1 = Vs[k1 >= 0 ? k1 : nb];
+        }
         double z0 = 0.0, z1 = 0.0;
         if (c.noise_on)
             normal_pair(p, stream, turn, 0u, key0, key1, z0, z1);
         double s0, c0, s1, c1;
         rf_phase(c.w_rf * t0, c.w_rf * t1, s0, c0, s1, c1);
-        kick_drift<NLR>(c, Vs, seen, s0, c0, z0, t0, d0);
-        kick_drift<NLR>(c, Vs, seen, s1, c1, z1, t1, d1);
+        kick_drift<NLR>(c, vb0, seen, s0, c0, z0, t0, d0);
+        kick_drift<NLR>(c, vb1, seen, s1, c1, z1, t1, d1);
     }
     epilogue<NLR>(c, hist_w, t0, d0, acc);
     if (two)
@@ -249,7 +256,7 @@ __device__ __forceinline__ T load_uniform(const T *p)
 
 // ---------------------------------------------------------------------------
 // k_push: each workgroup (256 threads) takes items g, g + grid, ... of the
-// item list; an item is one tile of 4096 particles of one bunch of one job.
+// item list; an item is one tile of 8192 particles of one bunch of one job.
 // PUSH = false is the bin-only prologue that produces the histogram,
 // deposits and moment sums of the present state without moving it.  Both
 // write the histogram into counts[(clock + 1) & 1]: during the push of turn
@@ -284,15 +291,15 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
         const uint32_t clock = __builtin_amdgcn_readfirstlane(J.clock[phase]);
         const uint32_t turn = clock;  // push of turn n runs with the clock at n
 
-        double *Vs = smem;
-        uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb);
-        double *red = smem + nb + ((J.nsub * nb + 1) >> 1);
+        double *Vs = smem;  // [nb + 1]
+        uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb + 1);
+        double *red = smem + nb + 1 + ((J.nsub * nb + 1) >> 1);
 
         for (int k = tid; k < J.nsub * nb; k += kPushThreads)
             hist[k] = 0u;
         if (PUSH && c.sr_on)
-            for (int k = tid; k < nb; k += kPushThreads)
-                Vs[k] = J.V[(size_t)b * nb + k] * c.inv_E0;
+            for (int k = tid; k <= nb; k += kPushThreads)
+                Vs[k] = k < nb ? J.V[(size_t)b * nb + k] * c.inv_E0 : 0.0;
         __syncthreads();
         uint32_t *hist_w = hist + (J.nsub > 0 ? (wave % J.nsub) * nb : 0);
 
