@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, vendor figure
+# Vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 VALU
+# instruction occupies a SIMD for four cycles), in lane-instructions/s.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
 BYTES_PER_PARTICLE_TURN = 32  # read tau, delta + write tau, delta (FP64)
 PMC_FILE = os.path.join(ROOT, "profiles", "push_c2_pmc.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_00391_amd", "csrc", "mbt_kernels.hip")
@@ -33,16 +36,17 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(particles_per_launch):
-    """HBM bytes per push launch from committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size), or
-    None when they are missing or were taken on a different kernel source."""
+def pmc_record(particles_per_launch):
+    """The committed rocprofv3 counter record of the push (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy kernel of known size, SQ instruction counts),
+    or None when it is missing or was taken on a different kernel source or
+    workload."""
     if not os.path.exists(PMC_FILE):
         return None
     d = json.load(open(PMC_FILE))
     if d.get("kernel_sha") != kernel_sha() or d.get("particles_per_launch") != particles_per_launch:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def make_tracker(w):
@@ -86,6 +90,51 @@ def cpu_baseline(w, budget_s):
                       f"warm-up turns, {dt:.1f} s"}
 
 
+def serving_sample(scale, budget_gb, wake):
+    """The serving mix (64 jobs with Poisson arrivals at 2/s, bunch counts
+    {1, 3, 40, 121, 363, 484}, 1e4-2e5 particles, 1000-20000 turns) with turns
+    and arrival times scaled by `scale` so a sample takes seconds: once
+    through the continuous-batching server (matrix-core wake `wake`), once as
+    the plain per-job FP64 tracker running the jobs one after another in
+    arrival order.  Returns throughput and p50/p99 job latency of both."""
+    import numpy as np
+    import torch
+    from paper_1809_00391_amd import serve
+    from paper_1809_00391_amd import workloads as wl
+    reqs = []
+    for i, (t, w) in enumerate(wl.serving_mix()):
+        turns = max(50, int(round(w.turns * scale)))
+        reqs.append(serve.Request(i, t * scale, w, turns))
+    total = sum(r.workload.M * r.workload.N * r.turns for r in reqs)
+    srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30), quantum=max(64, int(1000 * scale)),
+                       graph_turns=16, autotune=False, wake=wake)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = srv.run(reqs, keep_moments=False)
+    span = time.perf_counter() - t0
+    lat = serve.latency_percentiles(res)
+    # plain FP64 tracker, one job at a time in arrival order
+    t0 = time.perf_counter()
+    done = []
+    for r in sorted(reqs, key=lambda r: r.arrival_s):
+        now = time.perf_counter() - t0
+        if now < r.arrival_s:
+            time.sleep(r.arrival_s - now)
+        trk = serve.make_job(r.workload)
+        trk.track(r.turns, moments=False)
+        trk.close()
+        done.append(time.perf_counter() - t0 - r.arrival_s)
+    span_plain = time.perf_counter() - t0
+    return {"jobs": len(reqs), "scale": scale, "particle_turns": total,
+            "batched": {"value": total / span, "p50_s": lat["p50"], "p99_s": lat["p99"],
+                        "wake": wake, "hbm_budget_gb": budget_gb, "slices": srv.slices,
+                        "batches_built": srv.batches_built, "peak_bytes": srv.peak_bytes},
+            "plain_fp64_per_job": {"value": total / span_plain,
+                                   "p50_s": float(np.percentile(done, 50)),
+                                   "p99_s": float(np.percentile(done, 99))},
+            "unit": "macro-particle-turns/s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +145,11 @@ def main():
                     help="bracket every k-th push launch with HIP events")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.05,
+                    help="turn and arrival-time scale of the serving sample (0: skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=24.0,
+                    help="HBM budget of the serving sample's admission")
+    ap.add_argument("--serve-wake", default="bf16x2", choices=["fp64", "fp32", "bf16x2", "bf16x3"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -139,7 +193,15 @@ def main():
     value = particles * args.steps / elapsed
     push_avg_s = push_ms / 1e3 / push_n if push_n else float("nan")
     achieved = BYTES_PER_PARTICLE_TURN * particles / push_avg_s / 1e9 if push_n else float("nan")
-    traffic = traffic_from_profiles(particles)
+    pmc = pmc_record(particles)
+    traffic = pmc["hbm_bytes_per_launch"] if pmc else None
+    alu = None
+    if pmc and push_n:
+        lane_instr = pmc["valu_instructions_per_pair"] * particles / 2 / push_avg_s
+        alu = {"bound": "alu", "valu_instructions_per_pair": pmc["valu_instructions_per_pair"],
+               "achieved": lane_instr / 1e12, "peak": VALU_PEAK / 1e12,
+               "unit": "T lane-instructions/s", "frac": lane_instr / VALU_PEAK,
+               "source": "profiles/push_c2_pmc.json (SQ_INSTS_VALU of the same kernel source)"}
     finite = bool(torch.isfinite(torch.from_numpy(mom[-1])).all())
 
     out = {
@@ -172,11 +234,14 @@ def main():
             "avg_launch_us": push_avg_s * 1e6, "launches_timed": push_n,
             "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles,
             "prep_avg_us": prep_ms * 1e3 / max(prep_n, 1),
+            "alu": alu,
         },
         "moments_finite": finite,
     }
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    if args.serve_scale > 0:
+        out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.serve_wake)
     print(json.dumps(out), flush=True)
 
 

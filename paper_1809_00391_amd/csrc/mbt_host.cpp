@@ -1767,7 +1767,10 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
             G = (int)std::min<int64_t>(G, (int64_t)c->L.prof_slots * st[j]);
     }
     G &= ~1;  // an even number of turns leaves the launch phase where it began
-    if (G >= 2 && t + G <= nturns) {
+    // capture only when this call replays the graph at least twice (or it is
+    // already captured): a capture costs about as much as a few eager turns
+    const bool have = B->exec_turns == G && B->exec_phase == (int)(t & 1);
+    if (G >= 2 && (have ? t + G <= nturns : t + 2 * G <= nturns)) {
         if (B->exec_turns != G || B->exec_phase != (int)(t & 1))
             if ((rc = batch_capture(B, G, (int)(t & 1))))
                 return rc;

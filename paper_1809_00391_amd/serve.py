@@ -91,10 +91,12 @@ class Server:
     hbm_budget: device bytes the admitted jobs may hold together.
     quantum: most turns in one slice (admission and retirement happen between
     slices).  max_jobs: most jobs in one batch.  graph_turns, autotune: as in
-    mbt_batch_configure.  wake: arithmetic of the short-range wake.
+    mbt_batch_configure (the tuner's choices are cached per shape, but every
+    new batch composition is a new shape, so it is off by default).  wake:
+    arithmetic of the short-range wake.
     """
 
-    def __init__(self, hbm_budget, quantum=1000, max_jobs=64, graph_turns=16, autotune=True,
+    def __init__(self, hbm_budget, quantum=1000, max_jobs=64, graph_turns=16, autotune=False,
                  wake="fp64", clock=time.perf_counter):
         self.hbm_budget = int(hbm_budget)
         self.quantum = int(quantum)
