@@ -113,16 +113,20 @@ __host__ __device__ __noinline__ double exp_libm(double y) { return exp(y); }
 
 // exp(y): Taylor polynomial for |y| < 1e-3 (the long-range decay over one
 // bunch length: alpha*tau ~ 1e-5), otherwise the library.
+__host__ __device__ __forceinline__ double exp_taylor(double y)
+{
+    double p = 1.0 / 120.0;
+    p = horner(p, y, 1.0 / 24.0);
+    p = horner(p, y, 1.0 / 6.0);
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    return fma(p, y, 1.0);
+}
+
 __host__ __device__ __forceinline__ double exp_small(double y)
 {
-    if (fabs(y) < 1e-3) {
-        double p = 1.0 / 120.0;
-        p = horner(p, y, 1.0 / 24.0);
-        p = horner(p, y, 1.0 / 6.0);
-        p = fma(p, y, 0.5);
-        p = fma(p, y, 1.0);
-        return fma(p, y, 1.0);
-    }
+    if (fabs(y) < 1e-3)
+        return exp_taylor(y);
     return exp_libm(y);
 }
 

@@ -97,6 +97,27 @@ __device__ __forceinline__ int bin_of(const MapConst &c, double t)
     return (x >= 0.0 && x < (double)c.nbins) ? (int)x : -1;
 }
 
+// sin and cos of x: when every lane of the wavefront has |x| <= pi/4 the
+// Taylor polynomials apply directly (the pi/2 reduction would be the
+// identity, so the result is bit for bit the same); otherwise reduce first.
+__device__ __forceinline__ void sincos_wave(double x, double &s, double &c)
+{
+    constexpr double kPio4 = 0.7853981633974483;
+    if (__all(fabs(x) <= kPio4))
+        sincos_poly(x, s, c);
+    else
+        sincos_cw(x, s, c);
+}
+
+// exp(y) for the long-range decay across a bunch: the short Taylor form when
+// every lane has |y| < 1e-3 (the same branch exp_small takes lane by lane).
+__device__ __forceinline__ double exp_wave(double y)
+{
+    if (__all(fabs(y) < 1e-3))
+        return exp_taylor(y);
+    return exp_small(y);
+}
+
 // sin and cos of the RF phase x = w_rf tau of a pair of particles.  Near the
 // synchronous particle (every lane of the wavefront within |x| <= pi/4) the
 // Taylor polynomials apply directly; otherwise reduce by pi/2 first.
@@ -137,9 +158,9 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
         k -= vb;  // the bin's wake voltage, 0 outside the grid
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
-        const double e = exp_small(-c.lr_alpha[r] * t);
+        const double e = exp_wave(-c.lr_alpha[r] * t);
         double s, co;
-        sincos_cw(c.lr_wbar[r] * t, s, co);
+        sincos_wave(c.lr_wbar[r] * t, s, co);
         k -= e * fma(seen[r][0], co, -seen[r][1] * s);
     }
     double dn = (d + k) * c.one_minus_D;
@@ -180,9 +201,9 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
     acc[3] = fma(d, d, acc[3]);
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
-        const double e = exp_small(c.lr_alpha[r] * t);
+        const double e = exp_wave(c.lr_alpha[r] * t);
         double s, co;
-        sincos_cw(c.lr_wbar[r] * t, s, co);
+        sincos_wave(c.lr_wbar[r] * t, s, co);
         acc[4 + 2 * r] = fma(e, co, acc[4 + 2 * r]);
         acc[5 + 2 * r] = fma(-e, s, acc[5 + 2 * r]);
     }
@@ -323,7 +344,10 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
             uint32_t p = pair0 + (uint32_t)tid;
             dvec2 tv = *reinterpret_cast<const gptr<dvec2>>(tau + 2u * p);
             dvec2 dv = *reinterpret_cast<const gptr<dvec2>>(del + 2u * p);
-#pragma unroll 1
+#ifndef MBT_PUSH_UNROLL
+#define MBT_PUSH_UNROLL 1
+#endif
+#pragma unroll MBT_PUSH_UNROLL
             for (int s = 0; s < kPairsPerThread; ++s) {
                 dvec2 tn = tv, dn = dv;
                 if (s + 1 < kPairsPerThread) {
