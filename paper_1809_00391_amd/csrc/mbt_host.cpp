@@ -341,6 +341,16 @@ JobDesc job_desc(const mbt_ctx *c, uint32_t base, int prof_stride)
     return d;
 }
 
+// Which specialised push kernel fits the job (MapKind).
+int map_kind(const mbt_ctx *c)
+{
+    if (!c->sr_on || !(c->noise > 0.0))
+        return kMapGeneric;
+    if (!c->hc_on)
+        return kMapWakeNoise;
+    return c->hc.n == 3 ? kMapWakeNoiseHC3 : kMapGeneric;
+}
+
 // Push items of a job: (job, bunch, tile), bunch-major.
 void push_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 {
@@ -373,6 +383,7 @@ void wake_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 // resonators (a template parameter of the push).
 struct Group {
     int item0 = 0, nitems = 0, nlr = 0, nbins_max = 0, nsub_max = 0, grid = 0;
+    int map = kMapGeneric;  // compile-time map terms every job of the group shares
 };
 struct WakeGroup {
     int item0 = 0, nitems = 0, mode = 0, nbins_max = 0;
@@ -398,6 +409,7 @@ PushLaunch push_launch(const Engine &e, const Group &g, int phase)
     l.nbins_max = g.nbins_max;
     l.nsub_max = g.nsub_max;
     l.grid = g.grid > 0 ? std::min(g.grid, g.nitems) : g.nitems;
+    l.map = g.map;
     return l;
 }
 
@@ -492,6 +504,7 @@ Engine single_engine(const mbt_ctx *c)
     g.nbins_max = c->nbins();
     g.nsub_max = c->nsub;
     g.grid = c->push_grid;
+    g.map = map_kind(c);
     e.groups.push_back(g);
     e.wake_items = c->w<Item>(c->L.items_wake);
     if (c->sr_on && c->wake_mode != kWakeFP64) {
@@ -1590,6 +1603,7 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
         Group g;
         g.item0 = (int)pitems.size();
         g.nlr = nlr;
+        g.map = -1;
         for (int j = 0; j < njobs; ++j) {
             mbt_ctx *c = jobs[j];
             if (c->nlr() != nlr)
@@ -1597,7 +1611,11 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
             push_items(c, j, pitems);
             g.nbins_max = std::max(g.nbins_max, c->nbins());
             g.nsub_max = std::max(g.nsub_max, c->nsub);
+            const int k = map_kind(c);
+            g.map = (g.map < 0 || g.map == k) ? k : kMapGeneric;
         }
+        if (g.map < 0)
+            g.map = kMapGeneric;
         g.nitems = (int)pitems.size() - g.item0;
         if (g.nitems > 0)
             e.groups.push_back(g);

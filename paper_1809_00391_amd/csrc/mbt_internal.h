@@ -104,6 +104,13 @@ enum WakeMode {
     kWakeBF16x3 = 3,  // as above with three BF16 terms of W
 };
 
+// Terms of the single-particle map fixed at compile time in a push kernel.
+enum MapKind {
+    kMapGeneric = 0,       // every switch read from the map constants
+    kMapWakeNoise = 1,     // short-range wake and noise on, no harmonic cavity
+    kMapWakeNoiseHC3 = 2,  // as above with a third-harmonic cavity
+};
+
 // Launch descriptors.
 struct PushLaunch {
     int phase;                // slot of the turn counter this launch reads
@@ -114,6 +121,7 @@ struct PushLaunch {
     int nbins_max;
     int nsub_max;
     int grid;                 // workgroups; each takes items g, g + grid, ...
+    int map;                  // MapKind shared by every job of the items
 };
 struct PrepLaunch {
     int phase;

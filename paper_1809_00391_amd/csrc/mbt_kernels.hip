@@ -134,6 +134,27 @@ __device__ __forceinline__ void rf_phase(double x0, double x1, double &s0, doubl
     }
 }
 
+// Which terms of the map are on: read from the map constants in the generic
+// kernel (MAP = kMapGeneric), fixed at compile time in the specialisations
+// for the usual configurations, which frees the registers and branches the
+// flags cost.  A specialised kernel computes exactly what the generic one
+// does for the same constants.
+template <int MAP>
+__device__ __forceinline__ bool hc_on(const MapConst &c)
+{
+    return MAP == kMapGeneric ? c.hc_on != 0 : MAP == kMapWakeNoiseHC3;
+}
+template <int MAP>
+__device__ __forceinline__ bool sr_on(const MapConst &c)
+{
+    return MAP == kMapGeneric ? c.sr_on != 0 : true;
+}
+template <int MAP>
+__device__ __forceinline__ bool noise_on(const MapConst &c)
+{
+    return MAP == kMapGeneric ? c.noise_on != 0 : true;
+}
+
 // Kick, damping + quantum excitation, drift of one particle (Sec. 2.2 Eqs. 1,
 // 5, 2 with the Eq. 6 short-range kick and the long-range kick), all energy
 // terms in units of E0:
@@ -142,19 +163,19 @@ __device__ __forceinline__ void rf_phase(double x0, double x1, double &s0, doubl
 //   wake: vb = the bin's V/E0 (staged in LDS already divided by E0; read
 //         before the noise so that the LDS latency hides behind it)
 //   long range: Re[(V~/E0) exp((-alpha + i wbar) tau)]
-template <int NLR>
+template <int NLR, int MAP>
 __device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
                                            const double (&seen)[NLR > 0 ? NLR : 1][2], double sx,
                                            double cx, double z, double &t, double &d)
 {
     double k = fma(c.rf_a, cx, -c.rf_b * sx);
-    if (c.hc_on) {
+    if (hc_on<MAP>(c)) {
         double sn, cn;
-        multiple_angle(c.hc_n, sx, cx, sn, cn);
+        multiple_angle(MAP == kMapWakeNoiseHC3 ? 3 : c.hc_n, sx, cx, sn, cn);
         k += fma(c.hc_a, cn, -c.hc_b * sn);
     }
     k -= c.u0_e;
-    if (c.sr_on)
+    if (sr_on<MAP>(c))
         k -= vb;  // the bin's wake voltage, 0 outside the grid
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
@@ -164,7 +185,7 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
         k -= e * fma(seen[r][0], co, -seen[r][1] * s);
     }
     double dn = (d + k) * c.one_minus_D;
-    if (c.noise_on)
+    if (noise_on<MAP>(c))
         dn = fma(c.noise, z, dn);
     d = dn;
     t = fma(c.drift, dn, t);
@@ -186,11 +207,11 @@ __device__ __forceinline__ double wave_sum(double v)
 // The deposit phase is evaluated from the post-drift tau itself (not
 // rotated from the kick's phase), so the bin-only prologue of a resumed run
 // computes exactly the same sums as the push it replaces.
-template <int NLR>
+template <int NLR, int MAP>
 __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, double t, double d,
                                          double *acc)
 {
-    if (c.sr_on) {
+    if (sr_on<MAP>(c)) {
         const int k = bin_of(c, t);
         if (k >= 0)
             atomicAdd(&hist_w[k], 1u);
@@ -223,7 +244,7 @@ int conv_chunks(int nbins) { return nbins > 0 ? (nbins + kConvOut - 1) / kConvOu
 
 // Map and epilogue of the pair (t0, d0), (t1, d1) = particles 2p, 2p + 1
 // (the second only if `two`); the pushed coordinates are returned in place.
-template <int NLR, bool PUSH>
+template <int NLR, bool PUSH, int MAP>
 __device__ __forceinline__ void pair_compute(const MapConst &c, uint32_t key0, uint32_t key1,
                                              uint32_t turn, const double *Vs,
                                              const double (&seen)[NLR > 0 ? NLR : 1][2],
@@ -233,23 +254,23 @@ __device__ __forceinline__ void pair_compute(const MapConst &c, uint32_t key0, u
 {
     if (PUSH) {
         double vb0 = 0.0, vb1 = 0.0;
-        if (c.sr_on) {
+        if (sr_on<MAP>(c)) {
             const int nb = c.nbins;
             const int k0 = bin_of(c, t0), k1 = bin_of(c, t1);
             vb0 = Vs[k0 >= 0 ? k0 : nb];
             vb1 = Vs[k1 >= 0 ? k1 : nb];
         }
         double z0 = 0.0, z1 = 0.0;
-        if (c.noise_on)
+        if (noise_on<MAP>(c))
             normal_pair(p, stream, turn, 0u, key0, key1, z0, z1);
         double s0, c0, s1, c1;
         rf_phase(c.w_rf * t0, c.w_rf * t1, s0, c0, s1, c1);
-        kick_drift<NLR>(c, vb0, seen, s0, c0, z0, t0, d0);
-        kick_drift<NLR>(c, vb1, seen, s1, c1, z1, t1, d1);
+        kick_drift<NLR, MAP>(c, vb0, seen, s0, c0, z0, t0, d0);
+        kick_drift<NLR, MAP>(c, vb1, seen, s1, c1, z1, t1, d1);
     }
-    epilogue<NLR>(c, hist_w, t0, d0, acc);
+    epilogue<NLR, MAP>(c, hist_w, t0, d0, acc);
     if (two)
-        epilogue<NLR>(c, hist_w, t1, d1, acc);
+        epilogue<NLR, MAP>(c, hist_w, t1, d1, acc);
 }
 
 // Pointers known to address global memory: loads and stores through them
@@ -287,11 +308,12 @@ __device__ __forceinline__ T load_uniform(const T *p)
 // ---------------------------------------------------------------------------
 // Occupancy: without long-range resonators the push fits in 128 registers,
 // which allows four workgroups (four waves per SIMD) per compute unit; with
-// them, forcing that would spill.
+// one resonator three are kept (168 registers); with more, the compiler's
+// choice (two), since capping them spills.
 template <int NLR>
-constexpr int push_min_blocks() { return NLR == 0 ? 4 : 1; }
+constexpr int push_min_blocks() { return NLR == 0 ? 4 : (NLR == 1 ? 3 : 1); }
 
-template <int NLR, bool PUSH>
+template <int NLR, bool PUSH, int MAP>
 __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
     const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
     const int grid, const int phase)
@@ -318,7 +340,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
 
         for (int k = tid; k < J.nsub * nb; k += kPushThreads)
             hist[k] = 0u;
-        if (PUSH && c.sr_on)
+        if (PUSH && sr_on<MAP>(c))
             for (int k = tid; k <= nb; k += kPushThreads)
                 Vs[k] = k < nb ? J.V[(size_t)b * nb + k] * c.inv_E0 : 0.0;
         __syncthreads();
@@ -355,7 +377,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
                     dn = *reinterpret_cast<const gptr<dvec2>>(del + 2u * (p + kPushThreads));
                 }
                 double t0 = tv.x, t1 = tv.y, d0 = dv.x, d1 = dv.y;
-                pair_compute<NLR, PUSH>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, true,
+                pair_compute<NLR, PUSH, MAP>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, true,
                                         t0, t1, d0, d1, acc);
                 if (PUSH) {
                     *reinterpret_cast<gptr<dvec2>>(tau + 2u * p) = dvec2{t0, t1};
@@ -383,7 +405,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
                     t0 = tau[j0];
                     d0 = del[j0];
                 }
-                pair_compute<NLR, PUSH>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, two,
+                pair_compute<NLR, PUSH, MAP>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, two,
                                         t0, t1, d0, d1, acc);
                 if (PUSH) {
                     if (two) {
@@ -412,7 +434,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
             J.partials[((size_t)b * J.ntiles + tile) * kPartStride + tid] = sum;
         }
         // Merge the LDS sub-histograms into the bunch's histogram.
-        if (c.sr_on) {
+        if (sr_on<MAP>(c)) {
             uint32_t *out = J.counts + ((size_t)((clock + 1u) & 1u) * J.M + b) * nbx;
             for (int k = tid; k < nb; k += kPushThreads) {
                 uint32_t sum = 0;
@@ -824,16 +846,30 @@ __global__ __launch_bounds__(256) void k_philox(int64_t n, const uint32_t *ctr, 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+template <int NLR, int MAP>
+static void push_launch(const PushLaunch &l, bool push, size_t lds, hipStream_t s)
+{
+    constexpr int map = NLR == 1 ? MAP : kMapGeneric;
+    if (push)
+        hipLaunchKernelGGL((k_push<NLR, true, map>), dim3(l.grid), dim3(kPushThreads), lds, s,
+                           l.jobs, l.items, l.nitems, l.grid, l.phase);
+    else
+        hipLaunchKernelGGL((k_push<NLR, false, kMapGeneric>), dim3(l.grid), dim3(kPushThreads),
+                           lds, s, l.jobs, l.items, l.nitems, l.grid, l.phase);
+}
+
 template <int NLR>
 static hipError_t push_n(const PushLaunch &l, bool push, hipStream_t s)
 {
     const size_t lds = push_lds_bytes(l.nbins_max, l.nsub_max);
-    if (push)
-        hipLaunchKernelGGL((k_push<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s, l.jobs,
-                           l.items, l.nitems, l.grid, l.phase);
-    else
-        hipLaunchKernelGGL((k_push<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s, l.jobs,
-                           l.items, l.nitems, l.grid, l.phase);
+    // measured: without long-range resonators the specialisations spill at
+    // four waves per SIMD and run slower than the generic kernel; with one
+    // resonator they are faster; more resonators keep the generic kernel
+    switch (push && NLR == 1 ? l.map : kMapGeneric) {
+    case kMapWakeNoise: push_launch<NLR, kMapWakeNoise>(l, push, lds, s); break;
+    case kMapWakeNoiseHC3: push_launch<NLR, kMapWakeNoiseHC3>(l, push, lds, s); break;
+    default: push_launch<NLR, kMapGeneric>(l, push, lds, s); break;
+    }
     return hipGetLastError();
 }
 
