@@ -576,7 +576,8 @@ __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, d
 template <int NLR>
 __device__ __forceinline__ void prep_body(const PrepLaunch &L, const Item &item, const JobDesc &J,
                                           const uint32_t clock, double *psm)
-{    if (item.part == 0)
+{
+    if (item.part == 0)
         finish_sums<NLR>(J, item.bunch, clock);
     if (L.do_conv && J.c.sr_on) {
         if (J.wake_mode == kWakeFP64) {
