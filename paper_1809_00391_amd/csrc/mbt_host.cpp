@@ -86,7 +86,7 @@ struct Layout {
     size_t desc, items_push, items_prep, items_wake, clock, status, Wbf, Wf32;
     size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, mom, prof;
     size_t total;
-    int mom_slots, prof_slots, ntiles, nchunks, nwake;
+    int mom_slots, prof_slots, ntiles, nchunks, nwake, conv_out;
     int64_t ld;
     size_t state_bytes;
 };
@@ -97,7 +97,8 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     const int nbx = std::max(nb, 1);
     L.ld = (N + kRowAlign - 1) / kRowAlign * kRowAlign;
     L.ntiles = (int)((N + kTile - 1) / kTile);
-    L.nchunks = conv_chunks(nb);
+    L.conv_out = conv_width(M, nb);
+    L.nchunks = conv_chunks(nb, L.conv_out);
     L.nwake = nb > 0 ? ((M + kWakeBunches - 1) / kWakeBunches) * ((nb + kWakeBins - 1) / kWakeBins) : 0;
     // output rings: powers of two, about 16 MB each at most
     const size_t moment_row = (size_t)M * 4 * sizeof(double);
@@ -338,6 +339,7 @@ JobDesc job_desc(const mbt_ctx *c, uint32_t base, int prof_stride)
     d.prof_ring = c->w<uint32_t>(c->L.prof);
     d.status = c->w<uint32_t>(c->L.status);
     d.clock = c->w<uint32_t>(c->L.clock);
+    d.conv_out = c->L.conv_out;
     return d;
 }
 

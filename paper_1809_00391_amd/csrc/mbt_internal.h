@@ -19,7 +19,8 @@ constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // particle pairs per thr
 constexpr int kTile = kPushThreads * 2 * kPairsPerThread;  // particles per tile
 constexpr int kPartStride = 4 + 2 * kMaxLR;  // doubles per tile partial
 constexpr int kPrepThreads = 256;
-constexpr int kConvOut = 64;         // wake-potential bins per workgroup
+constexpr int kConvOutMax = 64;      // wake-potential bins per prep workgroup, at most
+constexpr int kConvOutMin = 16;      // ... and at least
 constexpr int kRowAlign = 64;        // particle rows padded to 64 doubles (512 B)
 
 // Per-turn constants of the single-particle map and the binning grid.
@@ -87,6 +88,7 @@ struct JobDesc {
     uint32_t *prof_ring;      // [prof_slots][M][nbins]
     uint32_t *status;         // bit 0: non-finite moment
     uint32_t *clock;          // [2] turn counter by launch phase (see below)
+    int conv_out;             // wake-potential bins per prep workgroup (16, 32 or 64)
 };
 
 // One unit of work: a tile (push) or a wake-potential chunk (prep) of a bunch.
@@ -156,7 +158,8 @@ hipError_t launch_init_gauss(double *tau, double *delta, int64_t ld, int64_t N, 
 hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1,
                          uint32_t *out, hipStream_t s);
 size_t push_lds_bytes(int nbins, int nsub);
-int conv_chunks(int nbins);
+int conv_chunks(int nbins, int conv_out);
+int conv_width(int M, int nbins);
 constexpr int kWakeBins = 64;     // bins per k_wake workgroup (16 per wavefront)
 constexpr int kWakeBunches = 16;  // bunches per k_wake workgroup
 

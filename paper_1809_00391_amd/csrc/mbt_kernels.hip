@@ -240,7 +240,22 @@ size_t push_lds_bytes(int nbins, int nsub)
     return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
 }
 
-int conv_chunks(int nbins) { return nbins > 0 ? (nbins + kConvOut - 1) / kConvOut : 1; }
+int conv_chunks(int nbins, int conv_out)
+{
+    return nbins > 0 ? (nbins + conv_out - 1) / conv_out : 1;
+}
+
+// Prep chunk width of a job: the widest of 64, 32, 16 bins that still gives
+// at least 256 prep workgroups (one per compute unit), so that few large
+// bunches get more threads per output bin and many bunches keep few
+// workgroups.
+int conv_width(int M, int nbins)
+{
+    int w = kConvOutMax;
+    while (w > kConvOutMin && (int64_t)M * conv_chunks(nbins, w) < 256)
+        w /= 2;
+    return w;
+}
 
 // Map and epilogue of the pair (t0, d0), (t1, d1) = particles 2p, 2p + 1
 // (the second only if `two`); the pushed coordinates are returned in place.
@@ -524,16 +539,18 @@ __device__ void finish_sums(const JobDesc &J, int b, uint32_t clock)
 }
 
 // Bins [k0, k1) of bunch b's wake potential (Sec. 2.3):
-// V[k] = qpp * sum_{m<=k} W[k-m] c[m].  Four threads per output bin, each
-// summing every fourth source bin with two accumulators; the four partial
-// sums are added in a fixed order.
+// V[k] = qpp * sum_{m<=k} W[k-m] c[m].  A workgroup takes w = conv_out
+// bins with K = 256 / w threads per output bin, each summing every K-th
+// source bin with two accumulators; the K partial sums are added in a fixed
+// order.
 __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, double *psm)
 {
     __shared__ int s_lo;
-    __shared__ double part[4][kConvOut];
+    __shared__ double part[kPrepThreads];
+    const int w = J.conv_out, K = kPrepThreads / w;
     const int tid = threadIdx.x;
     const int nb = J.c.nbins;
-    const int k0 = chunk * kConvOut, k1 = min(k0 + kConvOut, nb);
+    const int k0 = chunk * w, k1 = min(k0 + w, nb);
     const uint32_t *cin = J.counts + ((size_t)((clock + 1u) & 1u) * J.M + b) * nb;
     uint32_t *cclr = J.counts + ((size_t)(clock & 1u) * J.M + b) * nb;
     double *sW = psm;        // W[0 .. k1)
@@ -553,22 +570,26 @@ __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, d
         atomicMin(&s_lo, lo);
     __syncthreads();
     lo = s_lo;
-    const int o = tid & (kConvOut - 1), q = tid / kConvOut;  // output, quarter
+    const int o = tid % w, q = tid / w;  // output, way
     const int k = k0 + o;
     double acc0 = 0.0, acc1 = 0.0;
     if (k < k1) {
         int m = lo + q;
-        for (; m + 4 <= k; m += 8) {
+        for (; m + K <= k; m += 2 * K) {
             acc0 += sW[k - m] * sc[m];
-            acc1 += sW[k - m - 4] * sc[m + 4];
+            acc1 += sW[k - m - K] * sc[m + K];
         }
         if (m <= k)
             acc0 += sW[k - m] * sc[m];
     }
-    part[q][o] = acc0 + acc1;
+    part[q * w + o] = acc0 + acc1;
     __syncthreads();
-    if (tid < kConvOut && k < k1)
-        J.V[(size_t)b * nb + k] = J.qpp[b] * (((part[0][o] + part[1][o]) + part[2][o]) + part[3][o]);
+    if (tid < w && k < k1) {
+        double v = part[o];
+        for (int r = 1; r < K; ++r)
+            v += part[r * w + o];
+        J.V[(size_t)b * nb + k] = J.qpp[b] * v;
+    }
     for (int kk = k0 + tid; kk < k1; kk += kPrepThreads)
         cclr[kk] = 0u;
 }
@@ -585,7 +606,7 @@ __device__ __forceinline__ void prep_body(const PrepLaunch &L, const Item &item,
         } else {
             // the wake potential comes from k_wake; clear what the push fills next
             const int nb = J.c.nbins;
-            const int k0 = (int)item.part * kConvOut, k1 = min(k0 + kConvOut, nb);
+            const int k0 = (int)item.part * J.conv_out, k1 = min(k0 + J.conv_out, nb);
             uint32_t *cclr = J.counts + ((size_t)(clock & 1u) * J.M + item.bunch) * nb;
             for (int k = k0 + threadIdx.x; k < k1; k += kPrepThreads)
                 cclr[k] = 0u;
