@@ -151,6 +151,45 @@ __host__ __device__ __forceinline__ void multiple_angle(int n, double s1, double
     cn = c;
 }
 
+#ifndef MBT_FAST_NOISE_MATH
+#define MBT_FAST_NOISE_MATH 1
+#endif
+
+// (m - 1) / (m + 1) for m in [sqrt(1/2), sqrt(2)).  On the device with the
+// fast noise arithmetic: the hardware reciprocal refined by two Newton steps
+// and a final residual correction (within an ulp of the quotient).
+__host__ __device__ __forceinline__ double atanh_arg(double m)
+{
+#if defined(__HIP_DEVICE_COMPILE__) && MBT_FAST_NOISE_MATH
+    const double d = m + 1.0, n = m - 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    const double q = n * r;
+    return fma(fma(-d, q, n), r, q);
+#else
+    return (m - 1.0) / (m + 1.0);
+#endif
+}
+
+// sqrt(x) for the Box-Muller radius (x > 0).  On the device with the fast
+// noise arithmetic: the hardware reciprocal square root refined by one
+// coupled Newton step for sqrt(x) and 1/(2 sqrt(x)), then a residual
+// correction (within an ulp).
+__host__ __device__ __forceinline__ double sqrt_pos(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__) && MBT_FAST_NOISE_MATH
+    const double y = __builtin_amdgcn_rsq(x);
+    double r = x * y, h = 0.5 * y;
+    const double e = fma(-r, h, 0.5);
+    r = fma(r, e, r);
+    h = fma(h, e, h);
+    return fma(fma(-r, r, x), h, r);
+#else
+    return sqrt(x);
+#endif
+}
+
 // Natural logarithm of u in (0, 1] (the Box-Muller uniform).  u = m 2^e
 // with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1),
 // |s| < 0.172, from the series atanh(s) = s + s^3/3 + s^5/5 + ... truncated
@@ -164,7 +203,7 @@ __host__ __device__ __forceinline__ double log_unit(double u)
         m = m + m;
         e -= 1;
     }
-    const double s = (m - 1.0) / (m + 1.0);
+    const double s = atanh_arg(m);
     const double z = s * s;
     double p = 1.0 / 19.0;
     p = horner(p, z, 1.0 / 17.0);

@@ -79,7 +79,7 @@ __device__ __forceinline__ void normal_pair(uint32_t c0, uint32_t c1, uint32_t c
     philox10(c0, c1, c2, c3, k0, k1);
     const double u1 = u01_open0(c0, c1);
     const double u2 = u01_open0(c2, c3);
-    const double r = sqrt(-2.0 * log_unit(u1));
+    const double r = sqrt_pos(-2.0 * log_unit(u1));
     double s, c;
     sincos_2pi(u2, s, c);
     z0 = r * c;
