@@ -11,9 +11,11 @@ namespace mbt {
 // ---------------------------------------------------------------------------
 // FP64 sine/cosine/exponential for the per-particle map.
 //
-// sincos_poly: sin and cos of |r| <= pi/4 from their Taylor series (the
-// coefficient of r^n is +-1/n!), truncated where the first dropped term is
-// below 1e-16 of the result, evaluated in Horner form in r^2 with FMAs.
+// sincos_poly: sin and cos of |r| <= pi/4 as r + r z P(z) and
+// 1 - z/2 + z^2 Q(z), z = r^2, with P and Q of degree 5 minimising the largest
+// error of sin and cos on the interval (Remez exchange in 60-digit
+// arithmetic, gen_sincos_minimax.py beside this file: 3.4e-18 relative for
+// sin, 4.7e-20 for cos before rounding), in Horner form with FMAs.
 // sincos_cw: argument reduction by pi/2 after Cody and Waite (1980): with
 // k = rint(2x/pi), r = x - k*P1 - k*P2 where P1 is the double nearest pi/2
 // and P2 = pi/2 - P1, each step one FMA, then a quadrant swap.  Arguments
@@ -42,22 +44,20 @@ constexpr double kTwoOverPi = 0.6366197723675814;
 __host__ __device__ __forceinline__ void sincos_poly(double r, double &s, double &c)
 {
     const double z = r * r;
-    double ps = -1.0 / 1307674368000.0;           // -1/15!
-    ps = horner(ps, z, 1.0 / 6227020800.0);          //  1/13!
-    ps = horner(ps, z, -1.0 / 39916800.0);           // -1/11!
-    ps = horner(ps, z, 1.0 / 362880.0);              //  1/9!
-    ps = horner(ps, z, -1.0 / 5040.0);               // -1/7!
-    ps = horner(ps, z, 1.0 / 120.0);                 //  1/5!
-    ps = horner(ps, z, -1.0 / 6.0);                  // -1/3!
+    double ps = 1.5896827930152048e-10;           // S5
+    ps = horner(ps, z, -2.505075865328765e-08);   // S4
+    ps = horner(ps, z, 2.7557313695226595e-06);   // S3
+    ps = horner(ps, z, -0.0001984126982981695);   // S2
+    ps = horner(ps, z, 0.008333333333322425);     // S1
+    ps = horner(ps, z, -0.16666666666666632);     // S0
     s = fma(r * z, ps, r);
-    double pc = 1.0 / 20922789888000.0;           //  1/16!
-    pc = horner(pc, z, -1.0 / 87178291200.0);        // -1/14!
-    pc = horner(pc, z, 1.0 / 479001600.0);           //  1/12!
-    pc = horner(pc, z, -1.0 / 3628800.0);            // -1/10!
-    pc = horner(pc, z, 1.0 / 40320.0);               //  1/8!
-    pc = horner(pc, z, -1.0 / 720.0);                // -1/6!
-    pc = horner(pc, z, 1.0 / 24.0);                  //  1/4!
-    pc = fma(pc, z, -0.5);                           // -1/2! (inline constant)
+    double pc = -1.1359669889814536e-11;          // C5
+    pc = horner(pc, z, 2.0875723684860718e-09);   // C4
+    pc = horner(pc, z, -2.7557314355245e-07);     // C3
+    pc = horner(pc, z, 2.4801587289491837e-05);   // C2
+    pc = horner(pc, z, -0.0013888888888874138);   // C1
+    pc = horner(pc, z, 0.0416666666666666);       // C0
+    pc = fma(pc, z, -0.5);                        // -1/2 (inline constant)
     c = fma(z, pc, 1.0);
 }
 
