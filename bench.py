@@ -90,7 +90,7 @@ def cpu_baseline(w, budget_s):
                       f"warm-up turns, {dt:.1f} s"}
 
 
-def serving_sample(scale, budget_gb, wake):
+def serving_sample(scale, budget_gb, wake, fill):
     """The serving mix (64 jobs with Poisson arrivals at 2/s, bunch counts
     {1, 3, 40, 121, 363, 484}, 1e4-2e5 particles, 1000-20000 turns) with turns
     and arrival times scaled by `scale` so a sample takes seconds: once
@@ -107,7 +107,7 @@ def serving_sample(scale, budget_gb, wake):
         reqs.append(serve.Request(i, t * scale, w, turns))
     total = sum(r.workload.M * r.workload.N * r.turns for r in reqs)
     srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30), quantum=max(64, int(1000 * scale)),
-                       graph_turns=16, autotune=False, wake=wake)
+                       graph_turns=16, autotune=False, wake=wake, fill_particles=fill)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = srv.run(reqs, keep_moments=False)
@@ -127,7 +127,8 @@ def serving_sample(scale, budget_gb, wake):
     span_plain = time.perf_counter() - t0
     return {"jobs": len(reqs), "scale": scale, "particle_turns": total,
             "batched": {"value": total / span, "p50_s": lat["p50"], "p99_s": lat["p99"],
-                        "wake": wake, "hbm_budget_gb": budget_gb, "slices": srv.slices,
+                        "wake": wake, "hbm_budget_gb": budget_gb, "fill_particles": fill,
+                        "slices": srv.slices,
                         "batches_built": srv.batches_built, "peak_bytes": srv.peak_bytes},
             "plain_fp64_per_job": {"value": total / span_plain,
                                    "p50_s": float(np.percentile(done, 50)),
@@ -150,6 +151,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=24.0,
                     help="HBM budget of the serving sample's admission")
     ap.add_argument("--serve-wake", default="bf16x2", choices=["fp64", "fp32", "bf16x2", "bf16x3"])
+    ap.add_argument("--serve-fill", type=float, default=3.2e7,
+                    help="admit while the admitted jobs hold fewer particles than this (0: no limit)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -241,7 +244,8 @@ def main():
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     if args.serve_scale > 0:
-        out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.serve_wake)
+        out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.serve_wake,
+                                        args.serve_fill or None)
     print(json.dumps(out), flush=True)
 
 

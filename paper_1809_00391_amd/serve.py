@@ -93,17 +93,22 @@ class Server:
     slices).  max_jobs: most jobs in one batch.  graph_turns, autotune: as in
     mbt_batch_configure (the tuner's choices are cached per shape, but every
     new batch composition is a new shape, so it is off by default).  wake:
-    arithmetic of the short-range wake.
+    arithmetic of the short-range wake.  fill_particles: admit further jobs
+    only while the admitted jobs hold fewer macro-particles than this (enough
+    to fill the GPU); None admits whatever fits the budget.  With a fill
+    target, large jobs run nearly in arrival order and small ones are
+    batched together, which shortens the typical latency.
     """
 
     def __init__(self, hbm_budget, quantum=1000, max_jobs=64, graph_turns=16, autotune=False,
-                 wake="fp64", clock=time.perf_counter):
+                 wake="fp64", fill_particles=None, clock=time.perf_counter):
         self.hbm_budget = int(hbm_budget)
         self.quantum = int(quantum)
         self.max_jobs = int(max_jobs)
         self.graph_turns = int(graph_turns)
         self.autotune = bool(autotune)
         self.wake = wake
+        self.fill_particles = fill_particles
         self.clock = clock
         self.slices = 0
         self.batches_built = 0
@@ -124,6 +129,9 @@ class Server:
             # admission in arrival order while the footprint fits
             changed = False
             while pending and pending[0].arrival_s <= now and len(active) < self.max_jobs:
+                if (self.fill_particles is not None and active and
+                        sum(a[0].workload.M * a[0].workload.N for a in active) >= self.fill_particles):
+                    break
                 r = pending[0]
                 if r.job_id not in sizes:
                     sizes[r.job_id] = footprint(r.workload)
