@@ -1,4 +1,4 @@
-"""Coefficients of the sine and cosine polynomials in mbt_fastmath.h.
+"""Coefficients of the sine, cosine and logarithm polynomials in mbt_fastmath.h.
 
 On |x| <= pi/4, with z = x^2:
     sin x = x + x z P(z),   P of degree 5  (terms x^3 .. x^13)
@@ -6,6 +6,10 @@ On |x| <= pi/4, with z = x^2:
 P and Q minimise the largest error of sin and cos themselves, i.e. the
 weighted errors z (g_s - P) and z^2 (g_c - Q) with
     g_s(z) = (sin(sqrt z) / sqrt z - 1) / z,   g_c(z) = (cos(sqrt z) - 1 + z/2) / z^2,
+and for the logarithm's atanh series on |s| <= 3 - 2 sqrt(2),
+    atanh s = s + s z L(z),  L of degree 6  (terms s^3 .. s^15),
+minimising the relative error of atanh, i.e. z (g_l - L) with
+    g_l(z) = (atanh(sqrt z) / sqrt z - 1) / z,
 found by the Remez exchange algorithm in 60-digit arithmetic (mpmath).
 Run: python gen_sincos_minimax.py  (prints the coefficients and the
 achieved maximum errors).
@@ -28,6 +32,13 @@ def g_cos(z):
     if z == 0:
         return mp.mpf(1) / 24
     return (mp.cos(mp.sqrt(z)) - 1 + z / 2) / (z * z)
+
+
+def g_log(z):
+    if z == 0:
+        return mp.mpf(1) / 3
+    r = mp.sqrt(z)
+    return (mp.atanh(r) / r - 1) / z
 
 
 def remez(g, weight, deg=DEG, lo=mp.mpf(0), hi=ZMAX, iters=30):
@@ -81,6 +92,12 @@ def main():
     for k, v in enumerate(cc):
         print(f"  C{k} = {mp.nstr(v, 25)}  -> {float(v)!r}")
     print(f"  max |error of cos| ~ {mp.nstr(ec, 5)}")
+    smax = 3 - 2 * mp.sqrt(2)
+    cl, el = remez(g_log, lambda z: z, deg=6, hi=smax * smax)
+    print("atanh: s + s z L(z), L coefficients (z^0 .. z^6):")
+    for k, v in enumerate(cl):
+        print(f"  L{k} = {mp.nstr(v, 25)}  -> {float(v)!r}")
+    print(f"  max relative error of atanh ~ {mp.nstr(el, 5)}")
 
 
 if __name__ == "__main__":

@@ -192,9 +192,11 @@ __host__ __device__ __forceinline__ double sqrt_pos(double x)
 
 // Natural logarithm of u in (0, 1] (the Box-Muller uniform).  u = m 2^e
 // with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1),
-// |s| < 0.172, from the series atanh(s) = s + s^3/3 + s^5/5 + ... truncated
-// after s^19/19 (the next term is below 2^-55 of the sum); e ln 2 is added
-// with ln 2 split into a 32-bit head and a tail so that e * head is exact.
+// |s| <= 3 - 2 sqrt(2) = 0.1716, with atanh(s) = s + s z L(z), z = s^2, L the
+// degree-6 polynomial minimising the relative error on that interval (Remez,
+// gen_sincos_minimax.py: 1.2e-18 before rounding; the series
+// s + s^3/3 + s^5/5 + ... would need terms to s^19); e ln 2 is added with
+// ln 2 split into a 32-bit head and a tail so that e * head is exact.
 __host__ __device__ __forceinline__ double log_unit(double u)
 {
     int e;
@@ -205,15 +207,13 @@ __host__ __device__ __forceinline__ double log_unit(double u)
     }
     const double s = atanh_arg(m);
     const double z = s * s;
-    double p = 1.0 / 19.0;
-    p = horner(p, z, 1.0 / 17.0);
-    p = horner(p, z, 1.0 / 15.0);
-    p = horner(p, z, 1.0 / 13.0);
-    p = horner(p, z, 1.0 / 11.0);
-    p = horner(p, z, 1.0 / 9.0);
-    p = horner(p, z, 1.0 / 7.0);
-    p = horner(p, z, 1.0 / 5.0);
-    p = horner(p, z, 1.0 / 3.0);
+    double p = 0.07397974850291429;               // L6
+    p = horner(p, z, 0.07657025276056356);        // L5
+    p = horner(p, z, 0.09091782163059837);        // L4
+    p = horner(p, z, 0.11111099286592262);        // L3
+    p = horner(p, z, 0.1428571437119381);         // L2
+    p = horner(p, z, 0.19999999999707338);        // L1
+    p = horner(p, z, 0.3333333333333367);         // L0
     const double lm = fma(2.0 * s * z, p, 2.0 * s);
     const double ln2_hi = 0.693147180369123816490;    // ln 2 to 32 bits
     const double ln2_lo = 1.90821492927058770002e-10; // ln 2 - ln2_hi
