@@ -288,6 +288,7 @@ MapConst map_const(const mbt_ctx *c)
     m.sr_on = c->sr_on ? 1 : 0;
     m.noise_on = c->noise > 0.0 ? 1 : 0;
     m.nbins = c->nbins();
+    m.nbins_d = (double)c->nbins();
     if (c->sr_on) {
         m.tau_min = c->grid.tau_min_s;
         m.inv_delta = (double)c->grid.nbins / (c->grid.tau_max_s - c->grid.tau_min_s);

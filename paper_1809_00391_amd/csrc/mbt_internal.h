@@ -42,6 +42,7 @@ struct MapConst {
     int nbins;
     double tau_min;       // grid start [s]
     double inv_delta;     // nbins / (tau_max - tau_min)
+    double nbins_d;       // nbins as a double
     double lr_alpha[kMaxLR];  // omega_r / 2Q
     double lr_wbar[kMaxLR];   // sqrt(omega_r^2 - alpha^2)
 };

@@ -94,7 +94,10 @@ __device__ __forceinline__ void normal_pair(uint32_t c0, uint32_t c1, uint32_t c
 __device__ __forceinline__ int bin_of(const MapConst &c, double t)
 {
     const double x = (t - c.tau_min) * c.inv_delta;
-    return (x >= 0.0 && x < (double)c.nbins) ? (int)x : -1;
+    // both comparisons evaluated (no short-circuit), so this is a select,
+    // not a branch; NaN fails both
+    const bool in = (x >= 0.0) & (x < c.nbins_d);
+    return (int)(in ? x : -1.0);
 }
 
 // sin and cos of x: when every lane of the wavefront has |x| <= pi/4 the
@@ -175,8 +178,7 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
         k += fma(c.hc_a, cn, -c.hc_b * sn);
     }
     k -= c.u0_e;
-    if (sr_on<MAP>(c))
-        k -= vb;  // the bin's wake voltage, 0 outside the grid
+    k -= vb;  // the bin's wake voltage: 0 outside the grid or without a wake
 #pragma unroll
     for (int r = 0; r < NLR; ++r) {
         const double e = exp_wave(-c.lr_alpha[r] * t);
@@ -184,9 +186,8 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
         sincos_wave(c.lr_wbar[r] * t, s, co);
         k -= e * fma(seen[r][0], co, -seen[r][1] * s);
     }
-    double dn = (d + k) * c.one_minus_D;
-    if (noise_on<MAP>(c))
-        dn = fma(c.noise, z, dn);
+    // z = 0 without noise, and then the FMA returns dn unchanged
+    const double dn = fma(c.noise, z, (d + k) * c.one_minus_D);
     d = dn;
     t = fma(c.drift, dn, t);
 }
@@ -212,9 +213,9 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
                                          double *acc)
 {
     if (sr_on<MAP>(c)) {
+        // particles outside the grid go to the extra slot nb, never merged
         const int k = bin_of(c, t);
-        if (k >= 0)
-            atomicAdd(&hist_w[k], 1u);
+        atomicAdd(&hist_w[k >= 0 ? k : c.nbins], 1u);
     }
     acc[0] += t;
     acc[1] = fma(t, t, acc[1]);
@@ -231,11 +232,12 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
 }
 
 // LDS of the push: V/E0 of every bin plus a zero for "outside the grid",
-// the sub-histograms, and the wavefront partial sums.
+// the sub-histograms (every bin plus an "outside" slot), and the wavefront
+// partial sums.
 size_t push_lds_bytes(int nbins, int nsub)
 {
     size_t v = (size_t)(nbins + 1) * sizeof(double);
-    size_t h = (size_t)nsub * (size_t)nbins * sizeof(uint32_t);
+    size_t h = (size_t)nsub * (size_t)(nbins + 1) * sizeof(uint32_t);
     h = (h + 7) & ~(size_t)7;
     return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
 }
@@ -351,15 +353,16 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
 
         double *Vs = smem;  // [nb + 1]
         uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb + 1);
-        double *red = smem + nb + 1 + ((J.nsub * nb + 1) >> 1);
+        const int nbh = nb + 1;  // sub-histogram stride: the bins and the outside slot
+        double *red = smem + nb + 1 + ((J.nsub * nbh + 1) >> 1);
 
-        for (int k = tid; k < J.nsub * nb; k += kPushThreads)
+        for (int k = tid; k < J.nsub * nbh; k += kPushThreads)
             hist[k] = 0u;
         if (PUSH && sr_on<MAP>(c))
             for (int k = tid; k <= nb; k += kPushThreads)
                 Vs[k] = k < nb ? J.V[(size_t)b * nb + k] * c.inv_E0 : 0.0;
         __syncthreads();
-        uint32_t *hist_w = hist + (J.nsub > 0 ? (wave % J.nsub) * nb : 0);
+        uint32_t *hist_w = hist + (J.nsub > 0 ? (wave % J.nsub) * nbh : 0);
 
         double seen[NLR > 0 ? NLR : 1][2];
 #pragma unroll
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
             for (int k = tid; k < nb; k += kPushThreads) {
                 uint32_t sum = 0;
                 for (int q = 0; q < J.nsub; ++q)
-                    sum += hist[q * nb + k];
+                    sum += hist[q * nbh + k];
                 if (sum)
                     atomicAdd(&out[k], sum);
             }
