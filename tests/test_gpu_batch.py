@@ -133,3 +133,25 @@ def test_batch_job_against_oracle(cuda):
     b = tr.Batch(gs, graph_turns=8)
     mg = b.track(50)[3]
     assert moment_excess(mg, mo) <= 1e-9
+
+
+def test_output_rings_wrap_under_graphs(cuda):
+    """More turns than the moment ring holds (1024 rows for small jobs) and
+    more profile rows than the profile ring (64), in one call with graph
+    replay and in several calls of uneven length: the rows that come back are
+    those of the job tracked alone in one call."""
+    w = wl.C1.with_(N=3000, seed=21)
+    turns, stride = 2600, 13        # 2600 moment rows, 200 profile rows
+    print_case("ring wrap", turns=turns, stride=stride)
+    g = make_tracker(w)
+    m_alone, p_alone = g.track(turns, profiles_stride=stride)
+    gb = make_tracker(w)
+    b = tr.Batch([gb], graph_turns=16)
+    m1, p1 = b.track(turns, profiles_stride=[stride])
+    assert np.array_equal(m1[0], m_alone)
+    assert np.array_equal(p1[0], p_alone)
+    # the same turns in calls of 999 + 1001 + 600 turns on a fresh job
+    gc = make_tracker(w)
+    bc = tr.Batch([gc], graph_turns=16)
+    parts = [bc.track(n) for n in (999, 1001, 600)]
+    assert np.array_equal(np.concatenate([p[0] for p in parts]), m_alone)
