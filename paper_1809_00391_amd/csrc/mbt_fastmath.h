@@ -22,15 +22,17 @@ namespace mbt {
 // beyond 1e5 (never reached by particles near a bucket) use the library.
 // ---------------------------------------------------------------------------
 // One Horner step p*z + c, rounded once.  On the device it is spelled as a
-// single three-operand v_fma_f64: for a coefficient held in a vector
-// register the compiler otherwise emits the accumulating form, which first
-// copies the coefficient into the destination (one extra instruction per
-// step).  The result is the same correctly rounded FMA either way.
+// single three-operand v_fma_f64 whose coefficient operand is a scalar
+// register pair (a VOP3 instruction may read one): the coefficients are
+// loop-invariant, stay in scalar registers, and no vector register or copy
+// is spent on them, where the compiler's own choice copies each coefficient
+// into a vector register first.  The result is the same correctly rounded
+// FMA either way.
 __host__ __device__ __forceinline__ double horner(double p, double z, double c)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     double r;
-    __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "v"(c));
+    __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));
     return r;
 #else
     return fma(p, z, c);

@@ -323,12 +323,13 @@ __device__ __forceinline__ T load_uniform(const T *p)
 // n - 1.  Full tiles run a loop without bounds checks that loads the next
 // pair before computing the current one.
 // ---------------------------------------------------------------------------
-// Occupancy: without long-range resonators the push fits in 128 registers,
-// which allows four workgroups (four waves per SIMD) per compute unit; with
-// one resonator three are kept (168 registers); with more, the compiler's
-// choice (two), since capping them spills.
+// Occupancy: without long-range resonators the push fits in about 100
+// registers; with one resonator it is held to 128 (a few spills outside the
+// particle loop), so both run four workgroups (four waves per SIMD) per
+// compute unit; with more resonators, the compiler's choice (two), since
+// capping them spills inside the loop.
 template <int NLR>
-constexpr int push_min_blocks() { return NLR == 0 ? 4 : (NLR == 1 ? 3 : 1); }
+constexpr int push_min_blocks() { return NLR <= 1 ? 4 : 1; }
 
 template <int NLR, bool PUSH, int MAP>
 __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
