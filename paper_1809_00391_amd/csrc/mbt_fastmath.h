@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdint.h>
 
 namespace mbt {
 
@@ -63,13 +64,18 @@ __host__ __device__ __forceinline__ void sincos_poly(double r, double &s, double
     c = fma(z, pc, 1.0);
 }
 
-// x = q*pi/2 + r: rotate (sin r, cos r) into quadrant q.
+// x = q*pi/2 + r: rotate (sin r, cos r) into quadrant q.  The sine changes
+// sign where bit 1 of q is set, the cosine where bit 1 of q + 1 is; each
+// negation is that bit moved into the sign bit and XORed in (exact, and the
+// same value as a negation, signed zeros included).
 __host__ __device__ __forceinline__ void quadrant(int q, double sr, double cr, double &s, double &c)
 {
     const double s0 = (q & 1) ? cr : sr;
     const double c0 = (q & 1) ? sr : cr;
-    s = (q & 2) ? -s0 : s0;
-    c = ((q + 1) & 2) ? -c0 : c0;
+    const uint64_t sign_s = (uint64_t)(((uint32_t)q << 30) & 0x80000000u) << 32;
+    const uint64_t sign_c = (uint64_t)(((uint32_t)q + 1u) << 30 & 0x80000000u) << 32;
+    s = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, s0) ^ sign_s);
+    c = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, c0) ^ sign_c);
 }
 
 // Library sine and cosine for the rare huge argument, kept out of line so

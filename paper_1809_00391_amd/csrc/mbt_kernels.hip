@@ -49,6 +49,33 @@ __device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_
     x2 = y2;
 }
 
+// a ^ b ^ k in one instruction: v_bitop3_b32 evaluates any three-input
+// bitwise function given by its truth table, and 0x96 is the one that is 1
+// where an odd number of the inputs are 1.  k is wavefront-uniform (a round
+// key) and is read from a scalar register.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    __asm__("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// A round after the first, where every word of the state varies across the
+// wavefront: the same function as philox_round, with each three-way XOR in
+// one instruction instead of two.
+__device__ __forceinline__ void philox_round_v(uint32_t &x0, uint32_t &x1, uint32_t &x2,
+                                               uint32_t &x3, uint32_t k0, uint32_t k1)
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+    const uint32_t y2 = xor3((uint32_t)(p0 >> 32), x3, k1);
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+}
+
 __device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
                                          uint32_t k0, uint32_t k1)
 {
@@ -57,19 +84,27 @@ __device__ __forceinline__ void philox10(uint32_t &x0, uint32_t &x1, uint32_t &x
     // loop (twenty scalar registers), so each round adds its Weyl step with
     // one scalar instruction instead.
     __asm__ volatile("" : "+s"(k0), "+s"(k1));
+    // The first round in plain code: three of the four counter words are
+    // uniform, and the compiler folds their part into scalar instructions.
+    philox_round(x0, x1, x2, x3, k0, k1);
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        philox_round(x0, x1, x2, x3, k0, k1);
+    for (int r = 1; r < 10; ++r) {
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+        philox_round_v(x0, x1, x2, x3, k0, k1);
     }
 }
 
 // 53 random bits to a double in (0, 1]: never 0, so the logarithm is finite.
+// The value is u = (x >> 11) 2^-53 + 2^-54 with x = hi 2^32 + lo, rounded
+// once.  Spelled as hi 2^-32 + ((lo >> 11) 2^-53 + 2^-54): the inner scaling
+// and sum are exact ((2 (lo >> 11) + 1) 2^-54 needs 22 bits) and the FMA
+// rounds the exact total once, so the result is the same double, without
+// the 64-bit shift and the second conversion's scaling.
 __device__ __forceinline__ double u01_open0(uint32_t lo, uint32_t hi)
 {
-    const uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
-    return (double)(x >> 11) * 0x1.0p-53 + 0x1.0p-54;
+    const double low = ldexp((double)(lo >> 11), -53) + 0x1.0p-54;
+    return fma((double)hi, 0x1.0p-32, low);
 }
 
 // Box-Muller pair from one Philox block: z0 = r cos(theta), z1 = r sin(theta).
