@@ -90,6 +90,70 @@ def cpu_baseline(w, budget_s):
                       f"warm-up turns, {dt:.1f} s"}
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device bandwidth of the library's own streaming copy kernel
+    (mbt_stream_copy) over a buffer four times the Infinity Cache: bytes read
+    plus bytes written per second, best of `reps` timed copies."""
+    import torch
+    from paper_1809_00391_amd import tracker as tr
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    tr.stream_copy(a, b, s)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        tr.stream_copy(a, b, s)
+        e1.record(s)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    ok = bool(torch.equal(a, b))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9, ok
+
+
+def full_fill(turns, wake):
+    """The full-fill configuration (484 bunches x 1e5 particles, BB wake on
+    256 bins, HOM long-range resonator) tracked `turns` turns twice: by the
+    plain FP64 tracker (eager launches, FP64 VALU convolution) and in the
+    batched mixed-precision form (captured 16-turn graphs, launch shape tuned
+    online, wake potential on the matrix cores in `wake`).  Moments are
+    copied out in both.  Returns both throughputs."""
+    import torch
+    from paper_1809_00391_amd import tracker as tr
+    from paper_1809_00391_amd import workloads as wl
+    w = wl.PRESETS["c4"]
+    particles = w.M * w.N
+    res = {"workload": w.name, "turns_timed": turns, "unit": "macro-particle-turns/s"}
+    for form in ("plain_fp64", "batched_mixed"):
+        t = make_tracker(w)
+        b = None
+        if form == "batched_mixed":
+            t.set_wake_precision(wake)
+            b = tr.Batch([t], stream=t.stream, graph_turns=16, autotune=True)
+            run = lambda n: b.track(n, moments=True)
+        else:
+            run = lambda n: t.track(n, moments=True)
+        run(64)   # warm-up; the tuner measures its candidates here
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(turns)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[form] = {"value": particles * turns / dt, "ms_per_turn": dt * 1e3 / turns}
+        if b is not None:
+            res[form].update({"wake": wake, "graph_turns": 16, "autotune": True,
+                              "launch_groups": [list(g) for g in b.launch_info()]})
+            b.close()
+        t.close()
+        torch.cuda.empty_cache()
+    res["batched_over_plain"] = res["batched_mixed"]["value"] / res["plain_fp64"]["value"]
+    return res
+
+
 def serving_sample(scale, budget_gb, wake, fill):
     """The serving mix (64 jobs with Poisson arrivals at 2/s, bunch counts
     {1, 3, 40, 121, 363, 484}, 1e4-2e5 particles, 1000-20000 turns) with turns
@@ -153,6 +217,10 @@ def main():
     ap.add_argument("--serve-wake", default="bf16x2", choices=["fp64", "fp32", "bf16x2", "bf16x3"])
     ap.add_argument("--serve-fill", type=float, default=3.2e7,
                     help="admit while the admitted jobs hold fewer particles than this (0: no limit)")
+    ap.add_argument("--full-fill-turns", type=int, default=2000,
+                    help="turns of the full-fill plain vs batched comparison (0: skip)")
+    ap.add_argument("--copy-bw", type=int, default=1,
+                    help="measure the library copy kernel's bandwidth (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -206,6 +274,7 @@ def main():
                "unit": "T lane-instructions/s", "frac": lane_instr / VALU_PEAK,
                "source": "profiles/push_c2_pmc.json (SQ_INSTS_VALU of the same kernel source)"}
     finite = bool(torch.isfinite(torch.from_numpy(mom[-1])).all())
+    copy_gbs, copy_ok = copy_bandwidth() if args.copy_bw else (None, None)
 
     out = {
         "metric": "macro-particle-turns/s (FP64 plain vs batched mixed-prec) at 1 GPU; "
@@ -238,11 +307,15 @@ def main():
             "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles,
             "prep_avg_us": prep_ms * 1e3 / max(prep_n, 1),
             "alu": alu,
+            "copy_GBs": copy_gbs, "copy_exact": copy_ok,
+            "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
         },
         "moments_finite": finite,
     }
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    if args.full_fill_turns > 0:
+        out["full_fill"] = full_fill(args.full_fill_turns, args.serve_wake)
     if args.serve_scale > 0:
         out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.serve_wake,
                                         args.serve_fill or None)

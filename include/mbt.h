@@ -336,6 +336,15 @@ int mbt_batch_track(mbt_batch *batch, int64_t nturns, mbt_moments *const *out,
 int mbt_philox4x32_10(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1,
                       uint32_t *out, void *hip_stream);
 
+/* Device-to-device copy of `bytes` bytes from src to dst with the library's
+ * own streaming kernel (16-byte accesses): the achievable-bandwidth yardstick
+ * for the push's traffic (the measurement protocol compares the push with
+ * both this copy and the published HBM peak).  src and dst are device
+ * pointers, 16-byte aligned, not overlapping; bytes a multiple of 16 (0 is a
+ * no-op).  Asynchronous on hip_stream.  MBT_EINVAL on a violated condition
+ * (nothing is launched), MBT_EDEVICE if the launch fails. */
+int mbt_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,7 @@ SIGNATURES = {
     "mbt_batch_track": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mbt_philox4x32_10": (C.c_int, [C.c_int64, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p,
                                     C.c_void_p]),
+    "mbt_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
 }
 
 _lib = None

@@ -370,7 +370,7 @@ void prep_items(const mbt_ctx *c, int job, std::vector<Item> &out)
             out.push_back(Item{(uint16_t)job, (uint16_t)b, (uint32_t)k});
 }
 
-// Wake items of a job: (job, 16-bunch tile, 64-bin tile).
+// Wake items of a job: (job, 16-bunch tile, 16-bin output tile).
 void wake_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 {
     const int nb = c->nbins();
@@ -380,6 +380,9 @@ void wake_items(const mbt_ctx *c, int job, std::vector<Item> &out)
         for (int kt = 0; kt < (nb + kWakeBins - 1) / kWakeBins; ++kt)
             out.push_back(Item{(uint16_t)job, (uint16_t)bt, (uint32_t)kt});
 }
+
+// A job whose wake potential k_wake computes on the matrix cores.
+bool mfma_wake(const mbt_ctx *c) { return c->sr_on && c->wake_mode != kWakeFP64; }
 
 // Launch tables of a set of jobs whose descriptors and item lists are in
 // device memory.  Push items are grouped by the number of long-range
@@ -437,7 +440,7 @@ hipError_t enqueue_prep(const Engine &e, int phase, hipStream_t s)
     l.nlr_max = e.nlr_max;
     l.nbins_max = e.nbins_max;
     l.do_conv = 1;
-    hipError_t r = launch_prep(l, s);
+    hipError_t r = e.nprep > 0 ? launch_prep(l, s) : hipSuccess;
     for (const WakeGroup &g : e.wakes) {
         if (r != hipSuccess)
             break;
@@ -498,7 +501,7 @@ Engine single_engine(const mbt_ctx *c)
     e.push_items = c->w<Item>(c->L.items_push);
     e.prep_items = c->w<Item>(c->L.items_prep);
     e.njobs = 1;
-    e.nprep = c->M * c->L.nchunks;
+    e.nprep = mfma_wake(c) ? 0 : c->M * c->L.nchunks;  // k_wake does a matrix-core job's prep
     e.nlr_max = c->nlr();
     e.nbins_max = c->nbins();
     Group g;
@@ -1306,6 +1309,23 @@ int mbt_philox4x32_10(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t ke
     return MBT_OK;
 }
 
+int mbt_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream)
+{
+    if (bytes < 0 || (bytes % 16) != 0)
+        return MBT_EINVAL;
+    if (bytes == 0)
+        return MBT_OK;
+    if (!src || !dst || (reinterpret_cast<uintptr_t>(src) & 15u) ||
+        (reinterpret_cast<uintptr_t>(dst) & 15u))
+        return MBT_EINVAL;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+    if (a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
+        return MBT_EINVAL;  // overlapping ranges
+    if (launch_stream_copy(src, dst, bytes, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+        return MBT_EDEVICE;
+    return MBT_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1624,7 +1644,8 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
             e.groups.push_back(g);
     }
     for (int j = 0; j < njobs; ++j) {
-        prep_items(jobs[j], j, citems);
+        if (!mfma_wake(jobs[j]))
+            prep_items(jobs[j], j, citems);  // k_wake does a matrix-core job's prep
         e.nlr_max = std::max(e.nlr_max, jobs[j]->nlr());
         e.nbins_max = std::max(e.nbins_max, jobs[j]->nbins());
         B->wake_modes.push_back(jobs[j]->wake_mode);

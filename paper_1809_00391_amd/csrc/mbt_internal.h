@@ -158,10 +158,12 @@ hipError_t launch_init_gauss(double *tau, double *delta, int64_t ld, int64_t N, 
                              uint32_t key0, uint32_t key1, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1,
                          uint32_t *out, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+size_t wake_lds_bytes(int mode, int nbins_max);
 size_t push_lds_bytes(int nbins, int nsub);
 int conv_chunks(int nbins, int conv_out);
 int conv_width(int M, int nbins);
-constexpr int kWakeBins = 64;     // bins per k_wake workgroup (16 per wavefront)
+constexpr int kWakeBins = 16;     // output bins per k_wake workgroup (one 16 x 16 MFMA tile)
 constexpr int kWakeBunches = 16;  // bunches per k_wake workgroup
 
 }  // namespace mbt

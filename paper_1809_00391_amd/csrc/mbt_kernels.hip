@@ -639,18 +639,10 @@ __device__ __forceinline__ void prep_body(const PrepLaunch &L, const Item &item,
 {
     if (item.part == 0)
         finish_sums<NLR>(J, item.bunch, clock);
-    if (L.do_conv && J.c.sr_on) {
-        if (J.wake_mode == kWakeFP64) {
-            conv_chunk(J, item.bunch, (int)item.part, clock, psm);
-        } else {
-            // the wake potential comes from k_wake; clear what the push fills next
-            const int nb = J.c.nbins;
-            const int k0 = (int)item.part * J.conv_out, k1 = min(k0 + J.conv_out, nb);
-            uint32_t *cclr = J.counts + ((size_t)(clock & 1u) * J.M + item.bunch) * nb;
-            for (int k = k0 + threadIdx.x; k < k1; k += kPrepThreads)
-                cclr[k] = 0u;
-        }
-    }
+    // jobs whose wake potential comes from the matrix cores have no prep
+    // items: k_wake does their between-turn work
+    if (L.do_conv && J.c.sr_on)
+        conv_chunk(J, item.bunch, (int)item.part, clock, psm);
 }
 
 template <int NLR>
@@ -677,8 +669,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
 //           v_mfma_f32_16x16x16_bf16 accumulates sum_q T_q C_p in FP32 per
 //           part p; the parts are combined in FP64.
 // s is a power of two near max |W|, so the tables are O(1).  A workgroup
-// covers 64 bins x 16 bunches, one 16 x 16 output tile per wavefront; the
-// reduction over m stops at the diagonal.  MFMA 16x16 operand layout (lane l,
+// covers one 16 x 16 output tile (16 bins x 16 bunches); its four
+// wavefronts take interleaved 16-bin steps of the reduction over m, which
+// stops at the diagonal, and their four partial tiles are added in
+// wavefront order in FP64.  MFMA 16x16 operand layout (lane l,
 // element r): A[l % 16][4 (l / 16) + r], B[4 (l / 16) + r][l % 16], and the
 // result C[4 (l / 16) + r][l % 16]; for the f32 form with K = 4,
 // A[l % 16][l / 16] and B[l / 16][l % 16].
@@ -693,6 +687,86 @@ __device__ __forceinline__ short small_int_bf16(uint32_t v)
     return (short)(__float_as_uint((float)v) >> 16);
 }
 
+// Moments and deposit sums of bunch b by one wavefront (the calling lanes
+// are its 64 lanes): the additions of finish_sums's workgroup, in the same
+// order (its four 64-thread slices one after another, each slice's lanes
+// summing every 256th tile, then a butterfly), so the results are the same
+// doubles.  Used where a wavefront, not a workgroup, is free for the bunch.
+// A slice with no tile adds +0.0, which changes no total (a sum of tile
+// partials that start from +0.0 is never -0.0), so the slices past the
+// last tile are skipped.
+__device__ __forceinline__ void finish_sums_wave(const JobDesc &J, int b, uint32_t clock, int lane)
+{
+    const int np = 4 + 2 * J.nlr;
+    double tot[kPartStride];
+#pragma unroll
+    for (int i = 0; i < kPartStride; ++i)
+        tot[i] = 0.0;
+#pragma unroll 1
+    for (int w = 0; w < kPrepThreads / 64 && 64 * w < J.ntiles; ++w) {
+        double s[kPartStride];
+#pragma unroll
+        for (int i = 0; i < kPartStride; ++i)
+            s[i] = 0.0;
+        for (int t = 64 * w + lane; t < J.ntiles; t += kPrepThreads) {
+            const double *p = J.partials + ((size_t)b * J.ntiles + t) * kPartStride;
+#pragma unroll
+            for (int i = 0; i < kPartStride; ++i)
+                if (i < np)
+                    s[i] += p[i];
+        }
+#pragma unroll
+        for (int i = 0; i < kPartStride; ++i)
+            if (i < np) {
+                const double v = wave_sum(s[i]);
+                tot[i] = w == 0 ? v : tot[i] + v;
+            }
+    }
+    const int32_t rel = (int32_t)(clock - J.base);
+    if (lane == 0) {
+        const double invN = 1.0 / (double)J.N;
+        const double mt = tot[0] * invN, md = tot[2] * invN;
+        const double vt = tot[1] * invN - mt * mt, vd = tot[3] * invN - md * md;
+        if (rel >= 0) {
+            double *m = J.mom_ring + ((size_t)(rel & (J.mom_slots - 1)) * J.M + b) * 4;
+            m[0] = mt;
+            m[1] = md;
+            m[2] = sqrt(vt > 0.0 ? vt : 0.0);
+            m[3] = sqrt(vd > 0.0 ? vd : 0.0);
+        }
+        if (!isfinite(mt) || !isfinite(md) || !isfinite(vt) || !isfinite(vd))
+            atomicOr(J.status, 1u);
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxLR; ++i)
+        if (lane == i && i < 2 * J.nlr)
+            J.S[((size_t)(i >> 1) * J.M + b) * 2 + (i & 1)] = tot[4 + i];
+}
+
+// Bins of the count block staged in LDS at a time, and the row stride of the
+// staged block (in words): rows start 16 bytes apart modulo the 32 banks, so
+// the 16 rows a wavefront reads at once fall into different banks.
+constexpr int kWakeStage = 256;
+__host__ __device__ constexpr int wake_stage_stride(int width) { return ((width + 3) & ~3) + 4; }
+// Partial output tiles of the four wavefronts: [wave][part][element][lane].
+constexpr int kWakeRed = 4 * 4 * 4 * 64;
+
+size_t wake_lds_bytes(int mode, int nbins_max)
+{
+    const int kmax = std::min(nbins_max, 4096);
+    const size_t w = mode == kWakeFP32 ? (size_t)kmax * 4
+                                       : (size_t)(mode == kWakeBF16x2 ? 2 : 3) * kmax * 2;
+    const size_t c = (size_t)kWakeBunches * wake_stage_stride(std::min(kmax, kWakeStage)) * 4;
+    return ((w + 15) & ~(size_t)15) + c + (size_t)kWakeRed * sizeof(float);
+}
+
+// The whole between-turn work of a job whose wake potential is computed on
+// the matrix cores (it has no prep items).  A workgroup takes 16 bunches x
+// 16 output bins: it finishes the tile sums of its share of those bunches,
+// one wavefront per bunch; multiplies the wake table by the bunches'
+// histograms staged in LDS; records the histogram tile on profile turns;
+// clears the tile of the histogram buffer the next push fills; one
+// workgroup per job writes the next turn into the other counter slot.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
 {
@@ -701,94 +775,183 @@ __global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
     const JobDesc &J = L.jobs[item.job];
     const int nb = J.c.nbins, M = J.M;
     const int b0 = (int)item.bunch * kWakeBunches;
-    const int kt = (int)item.part * kWakeBins;
+    const int nbt = min(kWakeBunches, M - b0);  // bunches of this tile
+    const int kb = (int)item.part * kWakeBins;   // output bins kb .. kb + 15
+    const int nparts = (nb + kWakeBins - 1) / kWakeBins;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t clock = J.clock[L.phase];
     const uint32_t *cnt = J.counts + (size_t)((clock + 1u) & 1u) * M * nb;
     constexpr int NW = MODE == kWakeFP32 ? 1 : (MODE == kWakeBF16x2 ? 2 : 3);
 
-    // W (or its parts) at distances [0, kmax) in LDS
-    const int kmax = min(nb, kt + kWakeBins);
+    // W (or its parts) at distances [0, kmax) and the histograms of the
+    // tile's bunches, a block of bins at a time, are staged in LDS.  Every
+    // load of a pass is issued before its first store, and the first pass
+    // of both before the sums, so their memory latencies overlap.
+    const int kmax = min(nb, kb + kWakeBins);  // source bins [0, kmax) reach the tile
     float *wf = reinterpret_cast<float *>(wsm);
     uint16_t *wb = reinterpret_cast<uint16_t *>(wsm);
-    if (MODE == kWakeFP32) {
-        for (int k = tid; k < kmax; k += 256)
-            wf[k] = J.Wf32[k];
-    } else {
-        for (int q = 0; q < NW; ++q)
-            for (int k = tid; k < kmax; k += 256)
-                wb[q * kmax + k] = J.Wbf[(size_t)q * nb + k];
+    const int wbytes = MODE == kWakeFP32 ? kmax * 4 : NW * kmax * 2;
+    uint32_t *sc = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(wsm) +
+                                                ((wbytes + 15) & ~15));
+    const int cst = wake_stage_stride(min(kmax, kWakeStage));
+    float *red = reinterpret_cast<float *>(sc + kWakeBunches * cst);
+    float wv32[4];
+    uint16_t wv16[NW][4];
+    auto load_w = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + tid + 256 * u;
+            if (MODE == kWakeFP32) {
+                wv32[u] = k < kmax ? J.Wf32[k] : 0.f;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NW; ++q)
+                    wv16[q][u] = k < kmax ? J.Wbf[(size_t)q * nb + k] : (uint16_t)0;
+            }
+        }
+    };
+    auto store_w = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + tid + 256 * u;
+            if (k < kmax) {
+                if (MODE == kWakeFP32) {
+                    wf[k] = wv32[u];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NW; ++q)
+                        wb[q * kmax + k] = wv16[q][u];
+                }
+            }
+        }
+    };
+    uint32_t cv[kWakeBunches];
+    auto load_counts = [&](int mb, int width) {
+#pragma unroll
+        for (int r = 0; r < kWakeBunches; ++r)
+            cv[r] = (r < nbt && tid < width) ? cnt[(size_t)(b0 + r) * nb + mb + tid] : 0u;
+    };
+    auto store_counts = [&](int width) {
+#pragma unroll
+        for (int r = 0; r < kWakeBunches; ++r)
+            if (r < nbt && tid < width)
+                sc[r * cst + tid] = cv[r];
+    };
+    load_w(0);
+    load_counts(0, min(kWakeStage, kmax));
+
+    // Sums of the tile's bunches b0 + j with j = part, part + nparts, ...
+    // (every bunch of the tile exactly once over its workgroups), the i-th
+    // of them by wavefront i mod 4.
+    for (int j = (int)item.part, i = 0; j < nbt; j += nparts, ++i)
+        if ((i & 3) == wave)
+            finish_sums_wave(J, b0 + j, clock, lane);
+
+    store_w(0);
+    for (int k0 = 1024; k0 < kmax; k0 += 1024) {
+        load_w(k0);
+        store_w(k0);
     }
-    __syncthreads();
-    const int kb = kt + 16 * wave;  // first bin of this wavefront's tile
-    if (kb >= nb)
-        return;
+
     const int i = lane & 15, g = lane >> 4;
-    const int b = b0 + i;  // bunch of this lane's column
-    const bool bok = b < M;
-    const uint32_t *crow = cnt + (size_t)(bok ? b : 0) * nb;
+    const bool bok = i < nbt;      // this lane's column is a bunch of the job
     const bool rok = kb + i < nb;  // row of this lane's A operand inside the grid
     floatx4 acc[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
         acc[p] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int mend = min(nb, kb + 16);
     const int np = J.count_parts;
-    for (int m0 = 0; m0 < mend; m0 += 16) {
-        if (MODE == kWakeFP32) {
+    for (int mb = 0; mb < kmax; mb += kWakeStage) {
+        // histogram bins [mb, mb + width) of the tile's bunches
+        const int width = min(kWakeStage, kmax - mb);
+        if (mb > 0)
+            load_counts(mb, width);
+        __syncthreads();  // W staged; the previous block's readers are done
+        store_counts(width);
+        __syncthreads();
+        const uint32_t *crow = sc + (bok ? i : 0) * cst;  // bin m at crow[m - mb]
+        const int m1 = mb + width;
+        // this wavefront's steps: m0 = mb + 16 (wave + 4 t)
+        for (int m0 = mb + 16 * wave; m0 < m1; m0 += 64) {
+            if (MODE == kWakeFP32) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int m = m0 + 4 * s + g;
-                const int d = kb + i - m;
-                const float a = (rok && d >= 0) ? wf[d] : 0.f;
-                const float c = (bok && m < nb) ? (float)crow[m] : 0.f;
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, c, acc[0], 0, 0, 0);
-            }
-        } else {
-            const int mg = m0 + 4 * g;
-            uint32_t c[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                c[r] = (bok && mg + r < nb) ? crow[mg + r] : 0u;
-            bf16x4 a[NW];
-            const int d0 = kb + i - mg;
-#pragma unroll
-            for (int q = 0; q < NW; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    a[q][r] = (rok && d0 - r >= 0) ? (short)wb[q * kmax + d0 - r] : (short)0;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                if (p >= np)
-                    break;
-                bf16x4 bp;
+                for (int s = 0; s < 4; ++s) {
+                    const int m = m0 + 4 * s + g;
+                    const int d = kb + i - m;
+                    const float a = (rok && d >= 0) ? wf[d] : 0.f;
+                    const float c = (bok && m < m1) ? (float)crow[m - mb] : 0.f;
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, c, acc[0], 0, 0, 0);
+                }
+            } else {
+                const int mg = m0 + 4 * g;
+                uint32_t c[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    bp[r] = small_int_bf16((c[r] >> (8 * p)) & 255u);
+                    c[r] = (bok && mg + r < m1) ? crow[mg + r - mb] : 0u;
+                bf16x4 a[NW];
+                const int d0 = kb + i - mg;
 #pragma unroll
                 for (int q = 0; q < NW; ++q)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], bp, acc[p], 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        a[q][r] = (rok && d0 - r >= 0) ? (short)wb[q * kmax + d0 - r] : (short)0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    if (p >= np)
+                        break;
+                    bf16x4 bp;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        bp[r] = small_int_bf16((c[r] >> (8 * p)) & 255u);
+#pragma unroll
+                    for (int q = 0; q < NW; ++q)
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], bp, acc[p], 0, 0, 0);
+                }
             }
         }
     }
-    if (!bok)
-        return;
-    const double scale = J.qpp[b] * J.wake_scale;
+    // the four partial tiles, then each thread one element of the tile:
+    // column i = lane % 16, row 4 (lane / 16) + r with r = tid / 64
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            red[((wave * 4 + p) * 4 + r) * 64 + lane] = acc[p][r];
+    __syncthreads();
+    {
+        const int r = wave;  // element handled by this thread
         const int k = kb + 4 * g + r;
-        if (k >= nb)
-            continue;
-        double v = 0.0;
-        if (MODE == kWakeFP32) {
-            v = (double)acc[0][r];
-        } else {
-            double w = 1.0;
-            for (int p = 0; p < np; ++p, w *= 256.0)
-                v = fma(w, (double)acc[p][r], v);
+        if (bok && k < nb) {
+            const int nparts_sum = MODE == kWakeFP32 ? 1 : np;
+            double v = 0.0, w = 1.0;
+            for (int p = 0; p < nparts_sum; ++p, w *= 256.0) {
+                double sp = (double)red[((0 * 4 + p) * 4 + r) * 64 + lane];
+#pragma unroll
+                for (int ww = 1; ww < 4; ++ww)
+                    sp += (double)red[((ww * 4 + p) * 4 + r) * 64 + lane];
+                v = fma(w, sp, v);
+            }
+            J.V[(size_t)(b0 + i) * nb + k] = J.qpp[b0 + i] * J.wake_scale * v;
         }
-        J.V[(size_t)b * nb + k] = scale * v;
     }
+
+    // the histogram tile on every prof_stride-th turn of the call
+    const int32_t rel = (int32_t)(clock - J.base);
+    const int tw = kmax - kb;  // bins of this tile
+    if (J.prof_stride > 0 && rel >= 0 && rel % J.prof_stride == 0) {
+        const int row = (rel / J.prof_stride) & (J.prof_slots - 1);
+        for (int e = tid; e < nbt * tw; e += 256) {
+            const int r = e / tw, k = kb + e % tw;
+            J.prof_ring[((size_t)row * M + b0 + r) * nb + k] = cnt[(size_t)(b0 + r) * nb + k];
+        }
+    }
+    // clear the tile of the buffer the next push fills
+    uint32_t *cclr = J.counts + (size_t)(clock & 1u) * M * nb;
+    for (int e = tid; e < nbt * tw; e += 256)
+        cclr[(size_t)(b0 + e / tw) * nb + kb + e % tw] = 0u;
+    // the next turn's counter, in the slot no launch of this turn reads
+    if (item.bunch == 0 && item.part == 0 && tid == 0)
+        J.clock[L.phase ^ 1] = clock + 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -904,6 +1067,21 @@ __global__ __launch_bounds__(256) void k_philox(int64_t n, const uint32_t *ctr, 
     }
 }
 
+// Device-to-device copy in 16-byte elements, one per thread, in workgroups
+// of 256 (4 KiB each): of the shapes measured on the MI355X (grid-stride
+// loops with 4 or 8 loads in flight per thread, non-temporal accesses,
+// 4-16 KiB per workgroup) the many small workgroups reach the highest
+// bandwidth, above the runtime's own device copy.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4 *__restrict__ src,
+                                                     u32x4 *__restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        ((gptr<u32x4>)dst)[i] = ((gptr<const u32x4>)src)[i];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -978,16 +1156,16 @@ hipError_t launch_wake(const WakeLaunch &l, hipStream_t s)
 {
     if (l.nitems < 1 || l.nbins_max < 1)
         return hipErrorInvalidValue;
-    const int kmax = std::min(l.nbins_max, 4096);
+    const size_t lds = wake_lds_bytes(l.mode, l.nbins_max);
     switch (l.mode) {
     case kWakeFP32:
-        hipLaunchKernelGGL((k_wake<kWakeFP32>), dim3(l.nitems), dim3(256), (size_t)kmax * 4, s, l);
+        hipLaunchKernelGGL((k_wake<kWakeFP32>), dim3(l.nitems), dim3(256), lds, s, l);
         break;
     case kWakeBF16x2:
-        hipLaunchKernelGGL((k_wake<kWakeBF16x2>), dim3(l.nitems), dim3(256), (size_t)kmax * 4, s, l);
+        hipLaunchKernelGGL((k_wake<kWakeBF16x2>), dim3(l.nitems), dim3(256), lds, s, l);
         break;
     case kWakeBF16x3:
-        hipLaunchKernelGGL((k_wake<kWakeBF16x3>), dim3(l.nitems), dim3(256), (size_t)kmax * 6 + 8, s, l);
+        hipLaunchKernelGGL((k_wake<kWakeBF16x3>), dim3(l.nitems), dim3(256), lds, s, l);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1016,6 +1194,19 @@ hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t
     if (bx > 8192)
         bx = 8192;
     hipLaunchKernelGGL(k_philox, dim3((unsigned)bx), dim3(256), 0, s, n, ctr, key0, key1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
+{
+    const int64_t n = bytes / 16;
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t bx = (n + 255) / 256;
+    if (bx > (int64_t)UINT32_MAX)
+        return hipErrorInvalidValue;  // beyond 2^44 bytes
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)bx), dim3(256), 0, s,
+                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ def hc_flat_fraction(ring, n, frac):
 
 def philox4x32_10(ctr, key0, key1, stream=None):
     """mbt_philox4x32_10 on a uint32 CUDA tensor ctr of shape [n, 4]."""
-    assert ctr.is_cuda and ctr.dtype == torch.int32 or ctr.dtype == torch.uint32
+    assert ctr.is_cuda and ctr.dtype in (torch.int32, torch.uint32)
     ctr = ctr.contiguous()
     out = torch.empty_like(ctr)
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -57,6 +57,19 @@ def philox4x32_10(ctr, key0, key1, stream=None):
     if rc:
         raise MbtError(rc, "philox")
     return out
+
+
+def stream_copy(src, dst, stream=None):
+    """mbt_stream_copy: copy the bytes of CUDA tensor src into dst (same byte
+    size, contiguous, 16-byte aligned) with the library's streaming kernel."""
+    assert src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _abi.lib().mbt_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                    nbytes, C.c_void_p(s.cuda_stream))
+    if rc:
+        raise MbtError(rc, "stream copy")
 
 
 class Tracker:

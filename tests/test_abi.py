@@ -123,6 +123,19 @@ def test_no_synchronous_phase_is_rejected():
     t.set_harmonic_cavity(tr.hc_flat_fraction(wl.RING_R480, 3, 0.9))
 
 
+def test_stream_copy_argument_checks():
+    """Rejected before anything is launched: sizes that are not a multiple of
+    16, misaligned or overlapping ranges; a zero size is a no-op."""
+    L = _abi.lib()
+    assert L.mbt_stream_copy(None, None, 0, None) == 0
+    assert L.mbt_stream_copy(0x1000, 0x9000, 24, None) == -1
+    assert L.mbt_stream_copy(0x1000, 0x9000, -16, None) == -1
+    assert L.mbt_stream_copy(0x1008, 0x9000, 16, None) == -1
+    assert L.mbt_stream_copy(0x1000, 0x9004, 16, None) == -1
+    assert L.mbt_stream_copy(0x1000, 0x1010, 32, None) == -1
+    assert L.mbt_stream_copy(None, 0x9000, 16, None) == -1
+
+
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6, 7):
         assert isinstance(tr.strerror(code), str)

@@ -123,3 +123,45 @@ def test_growth_rate_bf16_matches_fp64(cuda):
     print(f"[growth rate] fp64 {rates['fp64']:.6g} /s  bf16x2 {rates['bf16x2']:.6g} /s", flush=True)
     assert rates["fp64"] > 0  # the mode grows (HOM drive above radiation damping)
     assert rates["bf16x2"] == pytest.approx(rates["fp64"], rel=2e-2)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["40 bunches", "71 tiles"])
+def test_matrix_core_job_between_turn_work(cuda, mode, case):
+    """A job whose wake potential comes from the matrix cores has no prep
+    launch: its moments, deposit sums, profile rows, histogram clearing and
+    turn counter come from the wake kernel (the sums by one wavefront per
+    bunch).  With the grid placed beside the bunches every histogram is
+    empty and the wake potential is zero in every arithmetic, so the job
+    must give the same doubles as the FP64 job, whose prep sums by whole
+    workgroups: moments, particles, phasors and profiles over 30 turns, in
+    two calls.  Cases: 40 bunches (a ragged 16-bunch tile, 200 bins in
+    four ragged 64-bin tiles, two long-range resonators) and 3 bunches of 71
+    push tiles (more tiles than one 64-lane slice sums)."""
+    if case == "40 bunches":
+        w = wl.Workload(name="lr, empty grid", ring=wl.RING_R480, buckets=tuple(range(0, 480, 12)),
+                        currents_A=tuple(1e-3 * (1 + 0.5 * np.sin(b)) for b in range(40)),
+                        N=3 * 8192 + 101, turns=0, seed=9, sigma_tau0=12e-12,
+                        sigma_delta0=8.6e-4, short_range=(wl.BB,),
+                        grid=(200, 300e-12, 400e-12), long_range=(wl.HOM, (3e5, 5e3, 2.21e9)))
+    else:
+        w = wl.Workload(name="many tiles, empty grid", ring=wl.RING_R480, buckets=(0, 5, 9),
+                        currents_A=(2e-3, 1e-3, 3e-3), N=70 * 8192 + 5, turns=0, seed=10,
+                        sigma_tau0=12e-12, sigma_delta0=8.6e-4, short_range=(wl.BB,),
+                        grid=(64, -400e-12, -300e-12), long_range=(wl.HOM,))
+    print_case("matrix-core between-turn work", mode=mode, case=case, M=w.M, N=w.N)
+    ref_job = make_tracker(w)
+    mc_job = make_tracker(w)
+    mc_job.set_wake_precision(mode)
+    for part in (17, 13):
+        m_ref, p_ref = ref_job.track(part, profiles_stride=4)
+        m_mc, p_mc = mc_job.track(part, profiles_stride=4)
+        assert np.array_equal(m_mc, m_ref)
+        assert np.array_equal(p_mc, p_ref) and not p_ref.any()
+    for b in (0, w.M - 1):
+        t_ref, d_ref = ref_job.get_particles(b)
+        t_mc, d_mc = mc_job.get_particles(b)
+        assert np.array_equal(t_mc, t_ref) and np.array_equal(d_mc, d_ref)
+    s_ref, s_mc = ref_job.get_state(), mc_job.get_state()
+    assert s_ref[0] == s_mc[0] == 30
+    assert np.array_equal(s_ref[2], s_mc[2])
