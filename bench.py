@@ -66,7 +66,20 @@ def make_tracker(w):
 
 def cpu_baseline(w, budget_s):
     """The oracle (as it stands) on this host's cores, on a bounded number of
-    turns of the same workload."""
+    turns of the same workload; then the same with one thread."""
+    from oracle import ref
+    allc = ref.threads()
+    out = _oracle_rate(w, budget_s)
+    ref.set_threads(1)
+    try:
+        one = _oracle_rate(w, budget_s / 3)
+    finally:
+        ref.set_threads(allc)
+    out["single_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    return out
+
+
+def _oracle_rate(w, budget_s):
     from oracle import ref
     s = ref.RefSim(w.ring)
     if w.hc_flat:
@@ -80,7 +93,7 @@ def cpu_baseline(w, budget_s):
     t0 = time.perf_counter()
     s.track(2)
     per_turn = (time.perf_counter() - t0) / 2
-    turns = int(max(3, min(1000, budget_s / max(per_turn, 1e-9))))
+    turns = int(max(2, min(1000, budget_s / max(per_turn, 1e-9))))
     t0 = time.perf_counter()
     s.track(turns)
     dt = time.perf_counter() - t0
@@ -154,6 +167,49 @@ def full_fill(turns, wake):
     return res
 
 
+# Table 4 of the paper: wall time of 20,000 turns of bunches of 1e5
+# macro-particles (radiation damping and quantum excitation on) on an 8-core
+# workstation (2x Intel E5-2609 v2), a 36-core workstation (2x Intel E5-2697
+# v4), a 576-core cluster (32x Intel Xeon Gold 6140) running the CPU code,
+# and an NVIDIA Tesla K40c running the GPU code; None where it gives none.
+PAPER_TABLE4_S = {
+    1: (810, 549, 232, 93),
+    2: (814, 558, 236, 157),
+    3: (832, 562, 240, 221),
+    10: (3596, 577, 266, 546),
+    20: (None, 757, 312, 1006),
+    121: (None, 2883, 922, 5860),
+    363: (None, 10931, 3165, 18754),
+}
+
+
+def paper_table4(turns):
+    """The bunch counts of Table 4 (1e5 macro-particles per bunch, radiation
+    damping and quantum excitation on, consecutive buckets of the 480-bucket
+    ring, broadband-resonator wake on 256 bins) tracked by the plain FP64
+    tracker for `turns` turns; the time of 20,000 turns is extrapolated
+    linearly (the per-turn cost is constant) and set beside the paper's."""
+    import torch
+    from paper_1809_00391_amd import workloads as wl
+    rows = []
+    for m, paper in PAPER_TABLE4_S.items():
+        w = wl.C3.with_(name=f"{m} bunches", buckets=tuple(range(m)), currents_A=(1e-3,) * m,
+                        long_range=(), N=100_000, seed=4)
+        t = make_tracker(w)
+        t.track(50, moments=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.track(turns, moments=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t.close()
+        torch.cuda.empty_cache()
+        rows.append({"bunches": m, "value": m * w.N * turns / dt,
+                     "s_per_20000_turns": dt * 20000 / turns,
+                     "paper_s": dict(zip(("cpu_8core", "cpu_36core", "cluster_576core", "k40c"), paper))})
+    return {"turns_timed": turns, "unit": "macro-particle-turns/s", "rows": rows}
+
+
 def serving_sample(scale, budget_gb, wake, fill):
     """The serving mix (64 jobs with Poisson arrivals at 2/s, bunch counts
     {1, 3, 40, 121, 363, 484}, 1e4-2e5 particles, 1000-20000 turns) with turns
@@ -217,6 +273,8 @@ def main():
     ap.add_argument("--serve-wake", default="bf16x2", choices=["fp64", "fp32", "bf16x2", "bf16x3"])
     ap.add_argument("--serve-fill", type=float, default=3.2e7,
                     help="admit while the admitted jobs hold fewer particles than this (0: no limit)")
+    ap.add_argument("--table4-turns", type=int, default=1000,
+                    help="turns of the paper's Table 4 bunch counts (0: skip)")
     ap.add_argument("--full-fill-turns", type=int, default=2000,
                     help="turns of the full-fill plain vs batched comparison (0: skip)")
     ap.add_argument("--copy-bw", type=int, default=1,
@@ -316,6 +374,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     if args.full_fill_turns > 0:
         out["full_fill"] = full_fill(args.full_fill_turns, args.serve_wake)
+    if args.table4_turns > 0:
+        out["paper_table4"] = paper_table4(args.table4_turns)
     if args.serve_scale > 0:
         out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.serve_wake,
                                         args.serve_fill or None)

@@ -349,6 +349,18 @@ int mbt_ref_threads(void)
 #endif
 }
 
+int mbt_ref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Synchronous phase: the RF (plus harmonic cavity) restores exactly U0 at
  * tau = 0, and the branch is chosen so that alpha_c * dV/dphase > 0 (the
  * stable one for either sign of the momentum compaction). */

@@ -165,6 +165,10 @@ int mbt_ref_derived(const mbt_ref_sim *s, double out[5]);
 /* Number of OpenMP threads the per-particle loop uses (1 without OpenMP). */
 int mbt_ref_threads(void);
 
+/* Threads for the per-particle loop from now on (n >= 1; results do not
+ * depend on it).  Returns the number in effect. */
+int mbt_ref_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

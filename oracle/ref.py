@@ -73,6 +73,7 @@ def lib():
             "mbt_ref_set_state": (C.c_int, [sims, C.c_int64, C.c_uint64, dp]),
             "mbt_ref_derived": (C.c_int, [sims, dp]),
             "mbt_ref_threads": (C.c_int, []),
+            "mbt_ref_set_threads": (C.c_int, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -175,6 +176,11 @@ def hc_flat_fraction(ring, n, frac):
 
 def threads():
     return lib().mbt_ref_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's per-particle loop from now on; returns the number in effect."""
+    return lib().mbt_ref_set_threads(int(n))
 
 
 # ---- simulation object ----------------------------------------------------

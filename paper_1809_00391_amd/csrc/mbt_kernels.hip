@@ -598,12 +598,27 @@ __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, d
         s_lo = k1;
     __syncthreads();
     int lo = k1;             // first occupied bin: nothing below it contributes
-    for (int k = tid; k < k1; k += kPrepThreads) {
-        sW[k] = J.W[k];
-        const uint32_t cnt = cin[k];
-        sc[k] = (double)cnt;
-        if (cnt && k < lo)
-            lo = k;
+    // every load of a pass is issued before its first store, so a pass costs
+    // one memory latency
+    for (int k0 = 0; k0 < k1; k0 += 4 * kPrepThreads) {
+        double wv[4];
+        uint32_t cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + tid + u * kPrepThreads;
+            wv[u] = k < k1 ? J.W[k] : 0.0;
+            cv[u] = k < k1 ? cin[k] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + tid + u * kPrepThreads;
+            if (k < k1) {
+                sW[k] = wv[u];
+                sc[k] = (double)cv[u];
+                if (cv[u] && k < lo)
+                    lo = k;
+            }
+        }
     }
     if (lo < k1)
         atomicMin(&s_lo, lo);
