@@ -400,6 +400,12 @@ struct Engine {
     const Item *prep_items = nullptr;
     const Item *wake_items = nullptr;
     int njobs = 0, nprep = 0, nlr_max = 0, nbins_max = 0;
+    // a single job: prep chunks per bunch and wake tiles per 16-bunch tile,
+    // and its turn counter, so that the between-turn kernels derive their
+    // items and read the counter without the tables (the push keeps the
+    // tables: two more arguments cost its one-resonator form registers)
+    int one_chunks = 0, one_wparts = 0;
+    const uint32_t *one_clock = nullptr;
     std::vector<Group> groups;
     std::vector<WakeGroup> wakes;  // jobs whose wake potential comes from k_wake
 };
@@ -417,6 +423,15 @@ PushLaunch push_launch(const Engine &e, const Group &g, int phase)
     l.grid = g.grid > 0 ? std::min(g.grid, g.nitems) : g.nitems;
     l.map = g.map;
     return l;
+}
+
+// Fill the single-job fields of an engine over job c (its items are the
+// bunch-major tables prep_items / wake_items build).
+void set_one_job(Engine &e, const mbt_ctx *c)
+{
+    e.one_chunks = c->L.nchunks;
+    e.one_wparts = c->nbins() > 0 ? (c->nbins() + kWakeBins - 1) / kWakeBins : 0;
+    e.one_clock = c->w<uint32_t>(c->L.clock);
 }
 
 hipError_t enqueue_push(const Engine &e, bool push, int phase, hipStream_t s)
@@ -440,6 +455,8 @@ hipError_t enqueue_prep(const Engine &e, int phase, hipStream_t s)
     l.nlr_max = e.nlr_max;
     l.nbins_max = e.nbins_max;
     l.do_conv = 1;
+    l.inner = e.one_chunks;
+    l.clk = e.one_clock;
     hipError_t r = e.nprep > 0 ? launch_prep(l, s) : hipSuccess;
     for (const WakeGroup &g : e.wakes) {
         if (r != hipSuccess)
@@ -451,6 +468,8 @@ hipError_t enqueue_prep(const Engine &e, int phase, hipStream_t s)
         w.nitems = g.nitems;
         w.mode = g.mode;
         w.nbins_max = g.nbins_max;
+        w.inner = e.one_wparts;
+        w.clk = e.one_clock;
         r = launch_wake(w, s);
     }
     return r;
@@ -520,6 +539,7 @@ Engine single_engine(const mbt_ctx *c)
         w.nbins_max = c->nbins();
         e.wakes.push_back(w);
     }
+    set_one_job(e, c);
     return e;
 }
 
@@ -1675,6 +1695,8 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
     e.wake_items = reinterpret_cast<const Item *>(B->work + B->off_wake);
     e.njobs = njobs;
     e.nprep = (int)citems.size();
+    if (njobs == 1)
+        set_one_job(e, jobs[0]);
     auto bail = [&](hipError_t r) {
         std::snprintf(B->err, sizeof B->err, "batch setup failed: %s", hipGetErrorString(r));
         mbt_batch_destroy(B);

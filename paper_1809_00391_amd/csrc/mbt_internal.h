@@ -134,14 +134,21 @@ struct PrepLaunch {
     int nlr_max;
     int nbins_max;
     int do_conv;              // 0: moments only (the state at the end of a call)
+    // One job only: items are (0, i / inner, i % inner) and the turn counter
+    // is clk[phase], so a workgroup need not read the item table before the
+    // descriptor, nor the descriptor before the counter.  inner = 0: tables.
+    int inner;
+    const uint32_t *clk;
 };
 struct WakeLaunch {
     int phase;
     const JobDesc *jobs;
-    const Item *items;        // (job, 16-bunch tile, 64-bin tile)
+    const Item *items;        // (job, 16-bunch tile, 16-bin output tile)
     int nitems;
     int mode;                 // WakeMode other than kWakeFP64; every job of the items has it
     int nbins_max;
+    int inner;                // as in PrepLaunch
+    const uint32_t *clk;
 };
 struct ScanLaunch {
     const JobDesc *jobs;

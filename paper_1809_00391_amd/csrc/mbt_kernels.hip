@@ -664,9 +664,11 @@ template <int NLR>
 __global__ __launch_bounds__(kPrepThreads) void k_prep(const PrepLaunch L)
 {
     extern __shared__ double psm[];
-    const Item item = L.items[blockIdx.x];
+    const int bx = blockIdx.x;
+    const Item item = L.inner > 0 ? Item{0, (uint16_t)(bx / L.inner), (uint32_t)(bx % L.inner)}
+                                  : L.items[bx];
     const JobDesc &J = L.jobs[item.job];
-    const uint32_t clock = J.clock[L.phase];
+    const uint32_t clock = L.clk ? L.clk[L.phase] : J.clock[L.phase];
     prep_body<NLR>(L, item, J, clock, psm);
     // the next turn's counter, in the slot no launch of this turn reads
     if (item.bunch == 0 && item.part == 0 && threadIdx.x == 0)
@@ -786,7 +788,9 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
 {
     extern __shared__ double wsm[];
-    const Item item = L.items[blockIdx.x];
+    const int bx = blockIdx.x;
+    const Item item = L.inner > 0 ? Item{0, (uint16_t)(bx / L.inner), (uint32_t)(bx % L.inner)}
+                                  : L.items[bx];
     const JobDesc &J = L.jobs[item.job];
     const int nb = J.c.nbins, M = J.M;
     const int b0 = (int)item.bunch * kWakeBunches;
@@ -794,7 +798,7 @@ __global__ __launch_bounds__(256) void k_wake(const WakeLaunch L)
     const int kb = (int)item.part * kWakeBins;   // output bins kb .. kb + 15
     const int nparts = (nb + kWakeBins - 1) / kWakeBins;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t clock = J.clock[L.phase];
+    const uint32_t clock = L.clk ? L.clk[L.phase] : J.clock[L.phase];
     const uint32_t *cnt = J.counts + (size_t)((clock + 1u) & 1u) * M * nb;
     constexpr int NW = MODE == kWakeFP32 ? 1 : (MODE == kWakeBF16x2 ? 2 : 3);
 
