@@ -128,7 +128,7 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2 * nbytes / best / 1e9, ok
 
 
-def full_fill(turns, wake):
+def full_fill(turns, wake, copy_gbs=None):
     """The full-fill configuration (484 bunches x 1e5 particles, BB wake on
     256 bins, HOM long-range resonator) tracked `turns` turns twice: by the
     plain FP64 tracker (eager launches, FP64 VALU convolution) and in the
@@ -151,12 +151,25 @@ def full_fill(turns, wake):
         else:
             run = lambda n: t.track(n, moments=True)
         run(64)   # warm-up; the tuner measures its candidates here
+        if b is None:
+            t.set_timing(8)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         run(turns)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[form] = {"value": particles * turns / dt, "ms_per_turn": dt * 1e3 / turns}
+        if b is None:
+            # this state (774 MB) is three times the Infinity Cache: the HBM case
+            push_ms, push_n, _, _ = t.get_timing()
+            if push_n:
+                push_s = push_ms / 1e3 / push_n
+                gbs = BYTES_PER_PARTICLE_TURN * particles / push_s / 1e9
+                res[form]["push_roofline"] = {
+                    "bound": "hbm", "avg_launch_us": push_s * 1e6, "launches_timed": push_n,
+                    "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles, "achieved": gbs,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    "frac_of_copy": gbs / copy_gbs if copy_gbs else None}
         if b is not None:
             res[form].update({"wake": wake, "graph_turns": 16, "autotune": True,
                               "launch_groups": [list(g) for g in b.launch_info()]})
@@ -373,7 +386,7 @@ def main():
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     if args.full_fill_turns > 0:
-        out["full_fill"] = full_fill(args.full_fill_turns, args.serve_wake)
+        out["full_fill"] = full_fill(args.full_fill_turns, args.serve_wake, copy_gbs)
     if args.table4_turns > 0:
         out["paper_table4"] = paper_table4(args.table4_turns)
     if args.serve_scale > 0:
