@@ -119,12 +119,21 @@ __host__ __device__ __forceinline__ void sincos_2pi(double u, double &s, double 
 
 __host__ __device__ __noinline__ double exp_libm(double y) { return exp(y); }
 
-// exp(y): Taylor polynomial for |y| < 1e-3 (the long-range decay over one
-// bunch length: alpha*tau ~ 1e-5), otherwise the library.
-__host__ __device__ __forceinline__ double exp_taylor(double y)
+// exp(y) for the long-range decay across a bunch (alpha*tau ~ 1e-5): the
+// Taylor polynomial of degree 3 for |y| < 1e-4 (truncation y^4/24 < 4.2e-18,
+// under 0.04 ulp of 1), of degree 4 for |y| < 1e-3 (y^5/120 < 8.4e-18),
+// otherwise the library.
+__host__ __device__ __forceinline__ double exp_taylor3(double y)
 {
-    double p = 1.0 / 120.0;
-    p = horner(p, y, 1.0 / 24.0);
+    double p = 1.0 / 6.0;
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    return fma(p, y, 1.0);
+}
+
+__host__ __device__ __forceinline__ double exp_taylor4(double y)
+{
+    double p = 1.0 / 24.0;
     p = horner(p, y, 1.0 / 6.0);
     p = fma(p, y, 0.5);
     p = fma(p, y, 1.0);
@@ -133,8 +142,11 @@ __host__ __device__ __forceinline__ double exp_taylor(double y)
 
 __host__ __device__ __forceinline__ double exp_small(double y)
 {
-    if (fabs(y) < 1e-3)
-        return exp_taylor(y);
+    const double a = fabs(y);
+    if (a < 1e-4)
+        return exp_taylor3(y);
+    if (a < 1e-3)
+        return exp_taylor4(y);
     return exp_libm(y);
 }
 

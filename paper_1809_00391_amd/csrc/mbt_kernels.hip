@@ -147,12 +147,13 @@ __device__ __forceinline__ void sincos_wave(double x, double &s, double &c)
         sincos_cw(x, s, c);
 }
 
-// exp(y) for the long-range decay across a bunch: the short Taylor form when
-// every lane has |y| < 1e-3 (the same branch exp_small takes lane by lane).
+// exp(y) for the long-range decay across a bunch: the degree-3 Taylor form
+// without a per-lane branch when every lane has |y| < 1e-4 (the branch
+// exp_small takes lane by lane there, so the result is the same).
 __device__ __forceinline__ double exp_wave(double y)
 {
-    if (__all(fabs(y) < 1e-3))
-        return exp_taylor(y);
+    if (__all(fabs(y) < 1e-4))
+        return exp_taylor3(y);
     return exp_small(y);
 }
 

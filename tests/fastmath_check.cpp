@@ -55,6 +55,17 @@ int main()
         report("exp_small", 0, er);
     }
     {
+        // the degree-3 range alone, densely
+        std::uniform_real_distribution<double> U(-1.2e-4, 1.2e-4);
+        long double er = 0;
+        for (int i = 0; i < 200000; ++i) {
+            double y = U(rng);
+            long double t = expl((long double)y);
+            er = fmaxl(er, fabsl((long double)mbt::exp_small(y) - t) / t);
+        }
+        report("exp_small_1e-4", 0, er);
+    }
+    {
         // log on the 53-bit uniform grid of (0, 1], including the extremes
         long double er = 0;
         for (int i = 0; i < 400000; ++i) {

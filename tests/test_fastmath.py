@@ -25,7 +25,7 @@ def test_fastmath_accuracy(tmp_path):
                     os.path.join(HERE, "fastmath_check.cpp")], check=True, capture_output=True)
     out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
     rows = [l.split() for l in out if l.strip()]
-    assert len(rows) == 16
+    assert len(rows) == 17
     for name, ea, er in rows:
         key = next(k for k in LIMITS if name.startswith(k))
         lim_a, lim_r = LIMITS[key]
