@@ -1,0 +1,71 @@
+"""Parity at the benchmark's full sizes, in the launch configurations
+bench.py times:
+- the eight-current scan (8 bunches of 1e6 macro-particles, harmonic
+  cavity, BB wake on 512 bins) and the full fill (484 bunches of 1e5, BB
+  on 256 bins + HOM), each run by the plain FP64 tracker;
+- the full fill also in the batched mixed-precision form (16-turn graphs,
+  online launch tuner, BF16x2 wake on the matrix cores).
+
+Both sides start from the same seeded particles.  Plain form: every
+coordinate after one turn within 1e-12, moments over the following turns
+within 1e-9.  Batched form: moments within 1e-4 of the bunch rms, the bound
+of its wake arithmetic (the mixed-precision tests derive it).  The oracle
+runs on the host's threads; one turn of either case takes it under a
+second."""
+import numpy as np
+import pytest
+
+from paper_1809_00391_amd import tracker as tr
+from paper_1809_00391_amd import workloads as wl
+
+from helpers import (COORD_RTOL, MOMENT_RTOL, coord_excess, make_oracle, make_tracker,
+                     moment_excess, set_same_particles)
+
+pytestmark = pytest.mark.gpu
+
+
+def print_case(name, **kw):
+    print(f"[gpu case] {name} {kw}", flush=True)
+
+
+@pytest.mark.parametrize("preset,turns", [("c2", 10), ("c4", 5)])
+def test_plain_tracker_full_size(cuda, preset, turns):
+    w = wl.PRESETS[preset]
+    print_case("full size plain", preset=preset, M=w.M, N=w.N, turns=turns)
+    o = make_oracle(w, init=False)
+    g = make_tracker(w, init=False)
+    set_same_particles(w, [o, g], w.N)
+    o.track(1)
+    g.track(1)
+    worst = 0.0
+    for b in range(w.M):
+        to, do = o.get_particles(b)
+        tg, dg = g.get_particles(b)
+        worst = max(worst, coord_excess(tg, to), coord_excess(dg, do))
+    print(f"[full size] {preset} one turn: max coordinate excess {worst:.2e}", flush=True)
+    assert worst <= COORD_RTOL
+    mo = o.track(turns)
+    mg = g.track(turns)
+    ex = moment_excess(mg, mo)
+    print(f"[full size] {preset} {turns} turns: max moment excess {ex:.2e}", flush=True)
+    assert ex <= MOMENT_RTOL
+    if w.long_range:
+        assert np.allclose(g.get_state()[2], o.get_state()[2], rtol=1e-9, atol=0)
+
+
+def test_batched_mixed_full_fill(cuda):
+    w = wl.PRESETS["c4"]
+    turns = 20
+    print_case("full size batched bf16x2", M=w.M, N=w.N, turns=turns)
+    o = make_oracle(w, init=False)
+    g = make_tracker(w, init=False)
+    g.set_wake_precision("bf16x2")
+    set_same_particles(w, [o, g], w.N)
+    b = tr.Batch([g], graph_turns=16, autotune=True)
+    mg = b.track(turns)[0]
+    b.close()
+    mo = o.track(turns)
+    sig = np.concatenate([mo[..., 2:4], mo[..., 2:4]], axis=-1)
+    dev = float(np.max(np.abs(mg - mo) / sig))
+    print(f"[full size] c4 batched bf16x2 {turns} turns: max deviation / rms {dev:.2e}", flush=True)
+    assert dev <= 1e-4
