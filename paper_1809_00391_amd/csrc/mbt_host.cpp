@@ -362,7 +362,7 @@ void push_items(const mbt_ctx *c, int job, std::vector<Item> &out)
             out.push_back(Item{(uint16_t)job, (uint16_t)b, (uint32_t)t});
 }
 
-// Prep items of a job: (job, bunch, 64-bin chunk).
+// Prep items of a job: (job, bunch, chunk of conv_out bins).
 void prep_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 {
     for (int b = 0; b < c->M; ++b)
@@ -454,7 +454,6 @@ hipError_t enqueue_prep(const Engine &e, int phase, hipStream_t s)
     l.nitems = e.nprep;
     l.nlr_max = e.nlr_max;
     l.nbins_max = e.nbins_max;
-    l.do_conv = 1;
     l.inner = e.one_chunks;
     l.clk = e.one_clock;
     hipError_t r = e.nprep > 0 ? launch_prep(l, s) : hipSuccess;

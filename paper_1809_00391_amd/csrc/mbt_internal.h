@@ -133,7 +133,6 @@ struct PrepLaunch {
     int nitems;
     int nlr_max;
     int nbins_max;
-    int do_conv;              // 0: moments only (the state at the end of a call)
     // One job only: items are (0, i / inner, i % inner) and the turn counter
     // is clk[phase], so a workgroup need not read the item table before the
     // descriptor, nor the descriptor before the counter.  inner = 0: tables.

@@ -333,22 +333,6 @@ template <class T>
 using gptr = __attribute__((address_space(1))) T *;
 typedef double dvec2 __attribute__((ext_vector_type(2)));  // one 16-byte access
 
-// A wavefront-uniform copy of *p held in scalar registers: the descriptors
-// live in memory the kernels also write, so the compiler cannot prove them
-// unchanged and would otherwise keep every field in vector registers.
-template <class T>
-__device__ __forceinline__ T load_uniform(const T *p)
-{
-    static_assert(sizeof(T) % 4 == 0, "word-sized descriptor");
-    T v;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
-        dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    return v;
-}
-
 // ---------------------------------------------------------------------------
 // k_push: each workgroup (256 threads) takes items g, g + grid, ... of the
 // item list; an item is one tile of 8192 particles of one bunch of one job.
@@ -504,8 +488,8 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
 }
 
 // ---------------------------------------------------------------------------
-// k_prep: one workgroup per (job, bunch, 64-bin chunk).  After the push of
-// turn n (the counter reads n) it finishes the tile sums of the state after
+// k_prep: one workgroup per (job, bunch, chunk of 16-64 bins).  After the
+// push of turn n (the counter reads n) it finishes the tile sums of the state after
 // turn n (moments into the ring row of that turn, deposit sums S), records
 // that state's histogram on profile turns, builds 64 bins of the wake
 // potential from it, and clears the histogram buffer the push of turn n + 1
@@ -657,7 +641,7 @@ __device__ __forceinline__ void prep_body(const PrepLaunch &L, const Item &item,
         finish_sums<NLR>(J, item.bunch, clock);
     // jobs whose wake potential comes from the matrix cores have no prep
     // items: k_wake does their between-turn work
-    if (L.do_conv && J.c.sr_on)
+    if (J.c.sr_on)
         conv_chunk(J, item.bunch, (int)item.part, clock, psm);
 }
 
