@@ -166,6 +166,7 @@ EDGE = {
     "sr_off": wl.C1.with_(ring=dict(wl.RING_R480, u0_eV=0.0, tau_long_s=float("inf"),
                                     sigma_delta=0.0), N=3000),
     "neg_alpha": wl.C1.with_(ring=dict(wl.RING_R480, alpha_c=-6e-4), N=5000, grid=(96, -80e-12, 80e-12)),
+    "max_bins": wl.C1.with_(N=50_000, grid=(4096, -80e-12, 80e-12)),
 }
 
 

@@ -35,15 +35,22 @@ def print_case(name, **kw):
 
 
 @pytest.mark.parametrize("mode", sorted(MODES))
-@pytest.mark.parametrize("case", ["c4-like", "mb-ragged"])
+@pytest.mark.parametrize("case", ["c4-like", "mb-ragged", "wide-600", "max-4096"])
 def test_wake_potential_within_bound(cuda, mode, case):
     if case == "c4-like":
         w = W4
-    else:  # ragged shapes: 200 bins (not a multiple of 64), 5 bunches, empty bunch
+    elif case == "mb-ragged":  # 200 bins (not a multiple of 16 or 64), 5 bunches, an empty one
         w = wl.Workload(name="mb", ring=wl.RING_R480, buckets=(0, 3, 4, 9, 200),
                         currents_A=(1e-3, 2.5e-3, 0.0, 1.5e-3, 4e-3), N=70_001, turns=0, seed=7,
                         sigma_tau0=20e-12, sigma_delta0=8.6e-4, short_range=(wl.BB,),
                         grid=(200, -150e-12, 150e-12), long_range=(wl.HOM,))
+    elif case == "wide-600":  # histograms staged in three blocks (256, 256, 88 bins)
+        w = wl.C1.with_(name="wide", buckets=(0, 1, 2), currents_A=(1e-3, 2e-3, 0.5e-3),
+                        N=60_000, grid=(600, -80e-12, 80e-12))
+    else:  # the largest grid the library accepts, 17 bunches (a second, one-bunch tile)
+        w = wl.C1.with_(name="max bins", buckets=tuple(range(17)),
+                        currents_A=tuple(1e-3 * (1 + 0.1 * b) for b in range(17)),
+                        N=30_000, grid=(4096, -80e-12, 80e-12))
     print_case("wake bound", mode=mode, case=case, M=w.M, N=w.N)
     g = make_tracker(w, init=False)
     g.set_wake_precision(mode)
