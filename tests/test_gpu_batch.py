@@ -155,3 +155,46 @@ def test_output_rings_wrap_under_graphs(cuda):
     bc = tr.Batch([gc], graph_turns=16)
     parts = [bc.track(n) for n in (999, 1001, 600)]
     assert np.array_equal(np.concatenate([p[0] for p in parts]), m_alone)
+
+
+@pytest.mark.parametrize("graph_turns", [0, 8])
+def test_mixed_arithmetic_batch(cuda, graph_turns):
+    """One batch holding an FP64 job (its between-turn work in the prep), a
+    BF16x2 and an FP32 job (theirs in the matrix-core wake kernel, no prep
+    items) and a job without a grid (prep sums only): every job gives bit for
+    bit what it gives tracked alone with the same arithmetic, profiles
+    included, over two calls."""
+    modes = ["fp64", "bf16x2", None, "fp32"]
+    print_case("mixed arithmetic batch", graph_turns=graph_turns, modes=modes)
+    turns1, turns2 = 23, 18
+
+    def job(j):
+        g = make_tracker(JOBS[j])
+        if modes[j] not in (None, "fp64"):
+            g.set_wake_precision(modes[j])
+        return g
+
+    alone = []
+    for j, w in enumerate(JOBS):
+        g = job(j)
+        if STRIDES[j]:
+            m1, p1 = g.track(turns1, profiles_stride=STRIDES[j])
+            m2, p2 = g.track(turns2, profiles_stride=STRIDES[j])
+        else:
+            m1, p1 = g.track(turns1), None
+            m2, p2 = g.track(turns2), None
+        alone.append((m1, p1, m2, p2, g.get_particles(w.M - 1), g.get_state()))
+    gs = [job(j) for j in range(len(JOBS))]
+    b = tr.Batch(gs, graph_turns=graph_turns)
+    r1 = b.track(turns1, profiles_stride=STRIDES)
+    r2 = b.track(turns2, profiles_stride=STRIDES)
+    for j, w in enumerate(JOBS):
+        m1, p1, m2, p2, x, st = alone[j]
+        assert np.array_equal(r1[0][j], m1) and np.array_equal(r2[0][j], m2), j
+        if STRIDES[j]:
+            assert np.array_equal(r1[1][j], p1) and np.array_equal(r2[1][j], p2), j
+        xb = gs[j].get_particles(w.M - 1)
+        assert np.array_equal(xb[0], x[0]) and np.array_equal(xb[1], x[1]), j
+        sb = gs[j].get_state()
+        assert sb[0] == st[0] and np.array_equal(sb[2], st[2]), j
+    b.close()
