@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configurations
 bench.py times:
 - the eight-current scan (8 bunches of 1e6 macro-particles, harmonic
-  cavity, BB wake on 512 bins) and the full fill (484 bunches of 1e5, BB
-  on 256 bins + HOM), each run by the plain FP64 tracker;
+  cavity, BB wake on 512 bins), the 3/4 fill (360 bunches of 1e5 and a
+  120-bucket gap, BB on 256 bins + HOM) and the full fill (484 bunches of
+  1e5, BB on 256 bins + HOM), each run by the plain FP64 tracker;
 - the full fill also in the batched mixed-precision form (16-turn graphs,
   online launch tuner, BF16x2 wake on the matrix cores).
 
@@ -10,7 +11,7 @@ Both sides start from the same seeded particles.  Plain form: every
 coordinate after one turn within 1e-12, moments over the following turns
 within 1e-9.  Batched form: moments within 1e-4 of the bunch rms, the bound
 of its wake arithmetic (the mixed-precision tests derive it).  The oracle
-runs on the host's threads; one turn of either case takes it under a
+runs on the host's threads; one turn of any case takes it under a
 second."""
 import numpy as np
 import pytest
@@ -28,7 +29,7 @@ def print_case(name, **kw):
     print(f"[gpu case] {name} {kw}", flush=True)
 
 
-@pytest.mark.parametrize("preset,turns", [("c2", 10), ("c4", 5)])
+@pytest.mark.parametrize("preset,turns", [("c2", 10), ("c3", 5), ("c4", 5)])
 def test_plain_tracker_full_size(cuda, preset, turns):
     w = wl.PRESETS[preset]
     print_case("full size plain", preset=preset, M=w.M, N=w.N, turns=turns)
