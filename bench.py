@@ -275,8 +275,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20000, help="timed turns")
     ap.add_argument("--warmup", type=int, default=200, help="untimed turns first")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
-    ap.add_argument("--timing-every", type=int, default=8,
-                    help="bracket every k-th push launch with HIP events")
+    ap.add_argument("--timing-every", type=int, default=32,
+                    help="bracket every k-th turn's launches with HIP events (each bracketed "
+                         "turn costs about 12 us of event records at c2; 0: none)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0: skip)")
     ap.add_argument("--serve-scale", type=float, default=0.05,
