@@ -334,7 +334,7 @@ def main():
         wall = time.perf_counter() - wall0
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(wall, gpu_ms / 1e3)
-    push_ms, push_n, prep_ms, prep_n = t.get_timing()
+    push_ms, push_n, _, _ = t.get_timing()
     particles = w.M * w.N
     value = particles * args.steps / elapsed
     push_avg_s = push_ms / 1e3 / push_n if push_n else float("nan")
@@ -380,7 +380,6 @@ def main():
             "traffic": traffic,
             "avg_launch_us": push_avg_s * 1e6, "launches_timed": push_n,
             "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles,
-            "prep_avg_us": prep_ms * 1e3 / max(prep_n, 1),
             "alu": alu,
             "copy_GBs": copy_gbs, "copy_exact": copy_ok,
             "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
