@@ -249,10 +249,13 @@ int mbt_set_state(mbt_ctx *ctx, int64_t turn, uint64_t seed, const double *phaso
 
 /* Kernel timing for measurement.  With every > 0, mbt_track records HIP
  * events on the bound stream around the push launch and around the
- * between-turn launches (phasor scan and prep) of every `every`-th turn (at
- * most 4096 turns per call) and adds their elapsed times to running totals; every = 0 switches it off and
- * clears the totals.  mbt_get_timing returns the totals in milliseconds and
- * the number of timed launches (any pointer may be NULL). */
+ * between-turn launches (phasor scan; prep or wake kernel) of every
+ * `every`-th turn (at most 4096 turns per call) and adds their elapsed times
+ * to running totals; every = 0 switches it off and clears the totals.  The
+ * event records themselves take GPU time (several microseconds per bracketed
+ * turn), so sparse brackets disturb a throughput measurement least.
+ * mbt_get_timing returns the totals in milliseconds and the number of timed
+ * launches (any pointer may be NULL). */
 int mbt_set_timing(mbt_ctx *ctx, int32_t every);
 int mbt_get_timing(const mbt_ctx *ctx, double *push_ms, int64_t *push_launches,
                    double *prep_ms, int64_t *prep_launches);
@@ -286,9 +289,11 @@ int mbt_set_wake_precision(mbt_ctx *ctx, int32_t mode);
 
 /* ---- Batches -------------------------------------------------------------
  * A batch advances several bound jobs (contexts on one device) together:
- * each turn is three launches that cover every bunch of every job -- the
- * phasor scan of all jobs, the push of all tiles (one launch per distinct
- * long-range resonator count), the prep of all bunches.  Each job keeps its
+ * each turn's launches cover every bunch of every job -- the phasor scan of
+ * all jobs with long-range resonators, the push of all tiles (one launch per
+ * distinct long-range resonator count), the between-turn work of all
+ * bunches (the prep for FP64-wake jobs, one wake launch per matrix-core
+ * arithmetic for the others).  Each job keeps its
  * own seed, turn counter, workspace and reduction layout, so its results are
  * bit for bit those of tracking it alone with mbt_track.  A job in a batch
  * must not be tracked on its own or rebound while the batch exists; destroy

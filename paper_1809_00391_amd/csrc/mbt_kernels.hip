@@ -2,10 +2,11 @@
 // CDNA4 (gfx950).
 //
 // One turn is two launches on the caller's stream (three with long-range
-// resonators, four with a matrix-core wake), each covering every bunch of
-// every job it is given (jobs are described by device-resident descriptors,
-// work by item lists, and each job's turn counter lives on the device, so a
-// turn can be captured once and replayed), in this order:
+// resonators; a batch mixing FP64 and matrix-core jobs adds the wake kernel
+// beside the prep), each covering every bunch of every job it is given (jobs
+// are described by device-resident descriptors, work by item lists, and each
+// job's turn counter lives on the device, so a turn can be captured once and
+// replayed), in this order:
 //   k_scan  (one workgroup per job, only with long-range resonators): the
 //           long-range phasors through the bunches in bucket order (a scan
 //           of affine maps);
@@ -15,11 +16,14 @@
 //           damping and quantum excitation; Eq. 2 drift), then -- on the new
 //           tau, which is exactly the tau the next turn bins -- the LDS
 //           histogram, the long-range deposit sums and the moment sums;
-//   k_prep  (per bunch, one workgroup per 64 bins): finishes the push's
-//           per-bunch sums (moments, Sec. 2.4, and long-range deposits) and
-//           builds each bunch's binned wake potential from its line density
-//           (Sec. 2.3), and writes the job's next turn counter;
-//   k_wake  (matrix-core wake modes only): the wake potential instead.
+//   k_prep  (FP64 wake; per bunch, one workgroup per chunk of 16-64 bins):
+//           finishes the push's per-bunch sums (moments, Sec. 2.4, and
+//           long-range deposits), builds each bunch's binned wake potential
+//           from its line density (Sec. 2.3), and writes the job's next turn
+//           counter;
+//   k_wake  (matrix-core wake modes, in place of k_prep; one workgroup per
+//           16 bunches x 16 bins): the same between-turn work, with the wake
+//           potential as a Toeplitz-by-histograms product on the MFMA units.
 // Particle coordinates are FP64 structure-of-arrays rows, one row per bunch;
 // each thread moves pairs of neighbouring particles with 16-byte loads and
 // stores, and one Philox block gives both particles of a pair their noise.
