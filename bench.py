@@ -29,11 +29,22 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, vendor figure
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 BYTES_PER_PARTICLE_TURN = 32  # read tau, delta + write tau, delta (FP64)
 PMC_FILE = os.path.join(ROOT, "profiles", "push_c2_pmc.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1809_00391_amd", "csrc", "mbt_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1809_00391_amd", "csrc", f)
+               for f in ("mbt_kernels.hip", "mbt_fastmath.h", "mbt_internal.h")]
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the device code: every source the kernels are built from, with
+    comments and blank lines removed (a comment changes no kernel)."""
+    import re
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 
 
 def pmc_record(particles_per_launch):
