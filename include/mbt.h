@@ -262,8 +262,9 @@ int mbt_get_timing(const mbt_ctx *ctx, double *push_ms, int64_t *push_launches,
 
 /* Launch shape of the push: nsub LDS sub-histograms per workgroup (0: a
  * default from nbins) and push_grid persistent workgroups (0: one workgroup
- * per tile of 8192 particles).  Neither changes any result bit: histograms
- * are integer sums and each tile's partial sums keep their order.
+ * per push tile, 8192 particles for all but small jobs).  Neither changes
+ * any result bit: histograms are integer sums and each tile's partial sums
+ * keep their order.
  * MBT_EINVAL if the LDS image of the push would exceed 64 KiB. */
 int mbt_set_launch(mbt_ctx *ctx, int32_t nsub, int32_t push_grid);
 

@@ -86,7 +86,7 @@ struct Layout {
     size_t desc, items_push, items_prep, items_wake, clock, status, Wbf, Wf32;
     size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, mom, prof;
     size_t total;
-    int mom_slots, prof_slots, ntiles, nchunks, nwake, conv_out;
+    int mom_slots, prof_slots, ntiles, ppt, nchunks, nwake, conv_out;
     int64_t ld;
     size_t state_bytes;
 };
@@ -96,7 +96,9 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     Layout L{};
     const int nbx = std::max(nb, 1);
     L.ld = (N + kRowAlign - 1) / kRowAlign * kRowAlign;
-    L.ntiles = (int)((N + kTile - 1) / kTile);
+    L.ppt = pairs_per_thread(M, N);
+    const int64_t tile = 2LL * kPushThreads * L.ppt;
+    L.ntiles = (int)((N + tile - 1) / tile);
     L.conv_out = conv_width(M, nb);
     L.nchunks = conv_chunks(nb, L.conv_out);
     L.nwake = nb > 0 ? ((M + kWakeBunches - 1) / kWakeBunches) * ((nb + kWakeBins - 1) / kWakeBins) : 0;
@@ -312,6 +314,7 @@ JobDesc job_desc(const mbt_ctx *c, uint32_t base, int prof_stride)
     d.N = c->N;
     d.M = c->M;
     d.ntiles = c->L.ntiles;
+    d.ppt = c->L.ppt;
     d.nsub = c->nsub;
     d.nlr = c->nlr();
     d.mom_slots = c->L.mom_slots;

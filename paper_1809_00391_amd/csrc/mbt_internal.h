@@ -15,8 +15,7 @@ constexpr int kMaxLR = 4;            // long-range resonators
 #define MBT_PAIRS_PER_THREAD 16
 #endif
 constexpr int kPushThreads = MBT_PUSH_THREADS;         // wavefronts of 64
-constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // particle pairs per thread per tile
-constexpr int kTile = kPushThreads * 2 * kPairsPerThread;  // particles per tile
+constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // most particle pairs per thread per tile
 constexpr int kPartStride = 4 + 2 * kMaxLR;  // doubles per tile partial
 constexpr int kPrepThreads = 256;
 constexpr int kConvOutMax = 64;      // wake-potential bins per prep workgroup, at most
@@ -62,6 +61,7 @@ struct JobDesc {
     int64_t N;                // particles per bunch
     int M;
     int ntiles;               // push tiles per bunch
+    int ppt;                  // particle pairs per thread in a push tile (pairs_per_thread)
     int nsub;                 // LDS sub-histograms in the push
     int nlr;                  // long-range resonators
     int mom_slots;            // moment ring rows (power of two)
@@ -169,6 +169,7 @@ size_t wake_lds_bytes(int mode, int nbins_max);
 size_t push_lds_bytes(int nbins, int nsub);
 int conv_chunks(int nbins, int conv_out);
 int conv_width(int M, int nbins);
+int pairs_per_thread(int M, int64_t N);
 constexpr int kWakeBins = 16;     // output bins per k_wake workgroup (one 16 x 16 MFMA tile)
 constexpr int kWakeBunches = 16;  // bunches per k_wake workgroup
 

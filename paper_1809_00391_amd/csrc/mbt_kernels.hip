@@ -287,6 +287,24 @@ int conv_chunks(int nbins, int conv_out)
     return nbins > 0 ? (nbins + conv_out - 1) / conv_out : 1;
 }
 
+// Particle pairs per thread in a job's push tiles: the most (16: tiles of
+// 8192 particles) unless the job then has fewer than 512 tiles, when the
+// largest of 8, 4, 2, 1 that gives at least 512 tiles (or 1) is taken: a
+// small job's turn is bound by the serial work of one tile, not by
+// bandwidth.  A function of the job's shape alone, so a job's tile partition
+// (and the order of its sums) is the same alone and in any batch.
+int pairs_per_thread(int M, int64_t N)
+{
+    int p = kPairsPerThread;
+    while (p > 1) {
+        const int64_t tile = 2LL * kPushThreads * p;
+        if ((int64_t)M * ((N + tile - 1) / tile) >= 512)
+            break;
+        p /= 2;
+    }
+    return p;
+}
+
 // Prep chunk width of a job: the widest of 64, 32, 16 bins that still gives
 // at least 256 prep workgroups (one per compute unit), so that few large
 // bunches get more threads per output bin and many bunches keep few
@@ -339,7 +357,8 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));  // one 16-byte access
 
 // ---------------------------------------------------------------------------
 // k_push: each workgroup (256 threads) takes items g, g + grid, ... of the
-// item list; an item is one tile of 8192 particles of one bunch of one job.
+// item list; an item is one tile of 512 ppt particles (8192 for all but
+// small jobs) of one bunch of one job.
 // PUSH = false is the bin-only prologue that produces the histogram,
 // deposits and moment sums of the present state without moving it.  Both
 // write the histogram into counts[(clock + 1) & 1]: during the push of turn
@@ -404,8 +423,9 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
             acc[i] = 0.0;
 
         // Indices within the bunch fit 32 bits (N <= 2^32, a pair index < 2^31).
-        const uint32_t pair0 = tile * (uint32_t)(kPushThreads * kPairsPerThread);
-        if ((int64_t)(pair0 + kPushThreads * kPairsPerThread) * 2 <= J.N) {
+        const int ppt = J.ppt;  // pairs per thread in this job's tiles
+        const uint32_t pair0 = tile * (uint32_t)(kPushThreads * ppt);
+        if ((int64_t)(pair0 + kPushThreads * ppt) * 2 <= J.N) {
             uint32_t p = pair0 + (uint32_t)tid;
             dvec2 tv = *reinterpret_cast<const gptr<dvec2>>(tau + 2u * p);
             dvec2 dv = *reinterpret_cast<const gptr<dvec2>>(del + 2u * p);
@@ -413,9 +433,9 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
 #define MBT_PUSH_UNROLL 1
 #endif
 #pragma unroll MBT_PUSH_UNROLL
-            for (int s = 0; s < kPairsPerThread; ++s) {
+            for (int s = 0; s < ppt; ++s) {
                 dvec2 tn = tv, dn = dv;
-                if (s + 1 < kPairsPerThread) {
+                if (s + 1 < ppt) {
                     tn = *reinterpret_cast<const gptr<dvec2>>(tau + 2u * (p + kPushThreads));
                     dn = *reinterpret_cast<const gptr<dvec2>>(del + 2u * (p + kPushThreads));
                 }
@@ -433,7 +453,7 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
         } else {
             const uint32_t n_last = (uint32_t)(J.N - 1);  // last particle index
 #pragma unroll 1
-            for (int s = 0; s < kPairsPerThread; ++s) {
+            for (int s = 0; s < ppt; ++s) {
                 const uint32_t p = pair0 + (uint32_t)(s * kPushThreads + tid);
                 const uint32_t j0 = 2u * p;
                 if (j0 > n_last)
