@@ -1518,9 +1518,13 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
     std::vector<std::vector<float>> best(cand.size());
     for (size_t gi = 0; gi < cand.size(); ++gi)
         best[gi].assign(cand[gi].size(), 1e30f);
-    std::vector<hipEvent_t> ev(2 * cand.size());
+    std::vector<hipEvent_t> ev(2 * cand.size(), nullptr);
     for (hipEvent_t &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            for (hipEvent_t made : ev)
+                if (made)
+                    (void)hipEventDestroy(made);
             *rc = fail(B, MBT_EDEVICE, "hipEventCreate failed");
             return 0;
         }
