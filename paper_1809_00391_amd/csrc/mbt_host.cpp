@@ -1567,7 +1567,16 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         for (size_t gi = 0; gi < cand.size(); ++gi) {
-            const size_t k = std::min_element(best[gi].begin(), best[gi].end()) - best[gi].begin();
+            size_t k = std::min_element(best[gi].begin(), best[gi].end()) - best[gi].begin();
+            // The default shape (default sub-histograms, one workgroup per
+            // tile) stays unless a candidate beats it by more than 2%: two
+            // turns per candidate do not resolve smaller differences.
+            const Group &g = B->eng.groups[gi];
+            const int dsub = g.nbins_max > 0 ? default_nsub(g.nbins_max) : 0;
+            for (size_t d = 0; d < cand[gi].size(); ++d)
+                if (cand[gi][d].nsub == dsub && cand[gi][d].grid == 0 &&
+                    best[gi][k] > 0.98f * best[gi][d])
+                    k = d;
             g_tune_cache[tune_key(B->eng.groups[gi])] = cand[gi][k];
             apply_choice(B, (int)gi, cand[gi][k]);
         }
