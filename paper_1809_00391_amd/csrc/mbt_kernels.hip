@@ -589,12 +589,11 @@ __device__ void finish_sums(const JobDesc &J, int b, uint32_t clock)
 // Bins [k0, k1) of bunch b's wake potential (Sec. 2.3):
 // V[k] = qpp * sum_{m<=k} W[k-m] c[m].  A workgroup takes w = conv_out
 // bins with K = 256 / w threads per output bin, each summing every K-th
-// source bin with two accumulators; the K partial sums are added in a fixed
-// order.
+// source bin with two accumulators; the K partial sums are added by a
+// butterfly across the K lanes (a fixed order).
 __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, double *psm)
 {
     __shared__ int s_lo;
-    __shared__ double part[kPrepThreads];
     const int w = J.conv_out, K = kPrepThreads / w;
     const int tid = threadIdx.x;
     const int nb = J.c.nbins;
@@ -609,18 +608,18 @@ __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, d
     int lo = k1;             // first occupied bin: nothing below it contributes
     // every load of a pass is issued before its first store, so a pass costs
     // one memory latency
-    for (int k0 = 0; k0 < k1; k0 += 4 * kPrepThreads) {
+    for (int ks = 0; ks < k1; ks += 4 * kPrepThreads) {
         double wv[4];
         uint32_t cv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + tid + u * kPrepThreads;
+            const int k = ks + tid + u * kPrepThreads;
             wv[u] = k < k1 ? J.W[k] : 0.0;
             cv[u] = k < k1 ? cin[k] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + tid + u * kPrepThreads;
+            const int k = ks + tid + u * kPrepThreads;
             if (k < k1) {
                 sW[k] = wv[u];
                 sc[k] = (double)cv[u];
@@ -633,26 +632,26 @@ __device__ void conv_chunk(const JobDesc &J, int b, int chunk, uint32_t clock, d
         atomicMin(&s_lo, lo);
     __syncthreads();
     lo = s_lo;
-    const int o = tid % w, q = tid / w;  // output, way
+    // the K ways of an output are consecutive lanes of one wavefront (K is
+    // 4, 8 or 16)
+    const int o = tid / K, q = tid % K;  // output, way
     const int k = k0 + o;
     double acc0 = 0.0, acc1 = 0.0;
     if (k < k1) {
         int m = lo + q;
         for (; m + K <= k; m += 2 * K) {
-            acc0 += sW[k - m] * sc[m];
-            acc1 += sW[k - m - K] * sc[m + K];
+            acc0 = fma(sW[k - m], sc[m], acc0);
+            acc1 = fma(sW[k - m - K], sc[m + K], acc1);
         }
         if (m <= k)
-            acc0 += sW[k - m] * sc[m];
+            acc0 = fma(sW[k - m], sc[m], acc0);
     }
-    part[q * w + o] = acc0 + acc1;
-    __syncthreads();
-    if (tid < w && k < k1) {
-        double v = part[o];
-        for (int r = 1; r < K; ++r)
-            v += part[r * w + o];
+    // fixed-order butterfly over the K ways, every lane taking part
+    double v = acc0 + acc1;
+    for (int off = K >> 1; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    if (q == 0 && k < k1)
         J.V[(size_t)b * nb + k] = J.qpp[b] * v;
-    }
     for (int kk = k0 + tid; kk < k1; kk += kPrepThreads)
         cclr[kk] = 0u;
 }
