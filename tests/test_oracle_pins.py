@@ -506,6 +506,42 @@ def test_checkpoint_resume_bitwise():
     assert np.array_equal(np.concatenate([first, second]), full)
 
 
+# ---------------------------------------------------------------------------
+# Bunch moments (Sec. 2.4): means and population rms of the state after a turn
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2001, 7])
+def test_moments_match_numpy_definition(N):
+    # Three bunches with wakes, long range and noise on; bunch 1 sits 5 sigma
+    # off in both coordinates, so a one-pass or shifted-reference slip would
+    # show, and bunch 2 is nearly a point (rms 1e-6 of its offset).  The
+    # oracle's moments of the state after the turn must be numpy's mean and
+    # std with ddof=0 of the particles it returns (a 1/(N-1) variance is off
+    # by 1/(2N) relative: 2.5e-4 at N = 2001, 7e-2 at N = 7).
+    s = ref.RefSim(R480)
+    s.set_fill([0, 3, 8], [1e-3, 2e-3, 0.5e-3])
+    s.set_short_range([wl.BB], (128, -120e-12, 120e-12))
+    s.set_long_range([wl.HOM])
+    s.alloc_particles(N, 11)
+    offs = [(0.0, 0.0, 1.0), (5 * 15e-12, 5 * 8.6e-4, 1.0), (40e-12, 1e-3, 1e-6)]
+    for b, (mt, md, scale) in enumerate(offs):
+        tau, delta = wl.gaussian_particles(70 + b, N, scale * 15e-12, scale * 8.6e-4,
+                                           mean_tau=mt, mean_delta=md)
+        s.set_particles(b, tau, delta)
+    mom = s.track(1)
+    assert mom.shape == (1, 3, 4)
+    for b in range(3):
+        tau, delta = s.get_particles(b)
+        expect = np.array([np.mean(tau), np.mean(delta), np.std(tau, ddof=0),
+                           np.std(delta, ddof=0)])
+        scale = np.array([np.std(tau), np.std(delta)] * 2)
+        scale = np.maximum(np.abs(expect), scale)
+        assert np.all(np.abs(mom[0, b] - expect) <= 1e-14 * scale), (b, mom[0, b], expect)
+        # the rms is the population one, not the sample one
+        sample = np.array([np.std(tau, ddof=1), np.std(delta, ddof=1)])
+        assert np.all(np.abs(mom[0, b, 2:] - sample) > 1e-6 * sample)
+
+
 def test_thread_count_does_not_change_results():
     code = (
         "import sys, numpy as np; sys.path.insert(0, %r); sys.path.insert(0, %r);"
