@@ -21,8 +21,10 @@
  *
  * General conventions
  *   - Every call returns MBT_OK (0) or a negative MBT_E* code; nothing throws
- *     or aborts across the ABI.  mbt_last_error() returns the message of the
- *     last failing call on a context.
+ *     or aborts across the ABI: a failed host allocation inside a call
+ *     returns MBT_ENOMEM, and a setter that fails leaves the previous
+ *     setting in force.  mbt_last_error() returns the message of the last
+ *     failing call on a context.
  *   - A context is used by one host thread at a time.
  *   - Host pointers are borrowed for the duration of the call only; output
  *     arrays are allocated by the caller with the sizes stated below.

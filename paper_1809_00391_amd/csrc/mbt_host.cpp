@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <mutex>
 #include <new>
@@ -246,6 +247,23 @@ int fail(C *c, int code, const char *fmt, ...)
         va_end(ap);
     }
     return code;
+}
+
+// Body of an entry point: no C++ exception crosses the C ABI.  A failed host
+// allocation (std::bad_alloc from a container) becomes MBT_ENOMEM, anything
+// else MBT_EDEVICE, with the message kept on the context or batch.
+template <class C, class F>
+int guarded(C *c, F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(c, MBT_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(c, MBT_EDEVICE, "internal error: %s", e.what());
+    } catch (...) {
+        return fail(c, MBT_EDEVICE, "internal error");
+    }
 }
 
 #define HIPCHK(ctx, expr)                                                                   \
@@ -585,6 +603,9 @@ int ring_alloc(mbt_ctx *c, RingOut &r, const void *dev, size_t row_bytes, int sl
     r.slots = slots;
     HIPCHK(c, hipHostMalloc((void **)&r.pin, (size_t)slots * row_bytes, hipHostMallocDefault));
     HIPCHK(c, hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+    // a flush adds at most two pieces after landing the previous ones, so
+    // the turn loop never allocates here
+    r.pending.reserve(2);
     return MBT_OK;
 }
 
@@ -756,596 +777,654 @@ const char *mbt_last_error(const mbt_ctx *ctx) { return ctx ? ctx->err : "null c
 
 int mbt_create(const mbt_ring *r, mbt_ctx **out)
 {
-    if (!out)
-        return MBT_EINVAL;
-    *out = nullptr;
-    if (!r)
-        return MBT_EINVAL;
-    if (!(r->energy_eV > 0.0) || !std::isfinite(r->energy_eV) || !(r->f_rf_Hz > 0.0) ||
-        !std::isfinite(r->f_rf_Hz) || !(r->v_rf_V > 0.0) || !std::isfinite(r->v_rf_V) ||
-        !std::isfinite(r->alpha_c) || r->alpha_c == 0.0 || !(r->u0_eV >= 0.0) ||
-        !std::isfinite(r->u0_eV) || !(r->tau_long_s > 0.0) || !(r->sigma_delta >= 0.0) ||
-        !std::isfinite(r->sigma_delta) || r->harmonic < 1 || !(r->u0_eV < r->v_rf_V))
-        return MBT_EINVAL;
-    mbt_ctx *c = new (std::nothrow) mbt_ctx();
-    if (!c)
-        return MBT_ENOMEM;
-    c->ring = *r;
-    c->T0 = (double)r->harmonic / r->f_rf_Hz;
-    c->T_rf = 1.0 / r->f_rf_Hz;
-    c->w_rf = kTwoPi * r->f_rf_Hz;
-    c->D = 2.0 * c->T0 / r->tau_long_s;  // per-turn damping of delta (Eq. 5)
-    c->noise = r->sigma_delta * std::sqrt(2.0 * c->D);
-    c->drift = r->alpha_c * c->T0;       // Eq. 2
-    if (solve_phi_s(c, false, c->hc, &c->phi_s) != MBT_OK) {
-        delete c;
-        return MBT_EINVAL;
-    }
-    if (hipGetDevice(&c->device) != hipSuccess)
-        c->device = 0;
-    *out = c;
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!out)
+            return MBT_EINVAL;
+        *out = nullptr;
+        if (!r)
+            return MBT_EINVAL;
+        if (!(r->energy_eV > 0.0) || !std::isfinite(r->energy_eV) || !(r->f_rf_Hz > 0.0) ||
+            !std::isfinite(r->f_rf_Hz) || !(r->v_rf_V > 0.0) || !std::isfinite(r->v_rf_V) ||
+            !std::isfinite(r->alpha_c) || r->alpha_c == 0.0 || !(r->u0_eV >= 0.0) ||
+            !std::isfinite(r->u0_eV) || !(r->tau_long_s > 0.0) || !(r->sigma_delta >= 0.0) ||
+            !std::isfinite(r->sigma_delta) || r->harmonic < 1 || !(r->u0_eV < r->v_rf_V))
+            return MBT_EINVAL;
+        mbt_ctx *c = new (std::nothrow) mbt_ctx();
+        if (!c)
+            return MBT_ENOMEM;
+        c->ring = *r;
+        c->T0 = (double)r->harmonic / r->f_rf_Hz;
+        c->T_rf = 1.0 / r->f_rf_Hz;
+        c->w_rf = kTwoPi * r->f_rf_Hz;
+        c->D = 2.0 * c->T0 / r->tau_long_s;  // per-turn damping of delta (Eq. 5)
+        c->noise = r->sigma_delta * std::sqrt(2.0 * c->D);
+        c->drift = r->alpha_c * c->T0;       // Eq. 2
+        if (solve_phi_s(c, false, c->hc, &c->phi_s) != MBT_OK) {
+            delete c;
+            return MBT_EINVAL;
+        }
+        if (hipGetDevice(&c->device) != hipSuccess)
+            c->device = 0;
+        *out = c;
+        return MBT_OK;
+    });
 }
 
 void mbt_destroy(mbt_ctx *ctx)
 {
-    if (!ctx)
-        return;
-    release_binding(ctx);
-    timer_free(ctx->timer);
-    delete ctx;
+    try {
+        if (!ctx)
+            return;
+        release_binding(ctx);
+        timer_free(ctx->timer);
+        delete ctx;
+    } catch (...) {
+        // teardown does not allocate; nothing may leave the ABI
+    }
 }
 
 int mbt_hc_flat_fraction(const mbt_ring *ring, int32_t n, double frac, mbt_hc *out)
 {
-    if (!ring || !out || n < 2 || !(frac > 0.0) || !std::isfinite(frac) || !(ring->v_rf_V > 0.0) ||
-        !(ring->u0_eV >= 0.0) || ring->alpha_c == 0.0)
-        return MBT_EINVAL;
-    // Flat potential: V(0) = U0, V'(0) = V''(0) = 0 for
-    // V(tau) = V_rf [sin(phi_s - w tau) + k sin(n phi_h - n w tau)].
-    const double u = ring->u0_eV / ring->v_rf_V;
-    const double n2 = (double)n * (double)n;
-    const double sin_s = n2 / (n2 - 1.0) * u;
-    const double k2 = 1.0 / n2 - u * u / (n2 - 1.0);
-    if (!(sin_s <= 1.0) || !(k2 > 0.0))
-        return MBT_EINVAL;
-    const double k = std::sqrt(k2);
-    double cos_s = std::sqrt(1.0 - sin_s * sin_s);
-    if (ring->alpha_c < 0.0)
-        cos_s = -cos_s;
-    out->n = n;
-    out->v_ratio = frac * k;
-    out->phase_n_rad = std::atan2(-sin_s / (k * n2), -cos_s / (k * (double)n));
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!ring || !out || n < 2 || !(frac > 0.0) || !std::isfinite(frac) || !(ring->v_rf_V > 0.0) ||
+            !(ring->u0_eV >= 0.0) || ring->alpha_c == 0.0)
+            return MBT_EINVAL;
+        // Flat potential: V(0) = U0, V'(0) = V''(0) = 0 for
+        // V(tau) = V_rf [sin(phi_s - w tau) + k sin(n phi_h - n w tau)].
+        const double u = ring->u0_eV / ring->v_rf_V;
+        const double n2 = (double)n * (double)n;
+        const double sin_s = n2 / (n2 - 1.0) * u;
+        const double k2 = 1.0 / n2 - u * u / (n2 - 1.0);
+        if (!(sin_s <= 1.0) || !(k2 > 0.0))
+            return MBT_EINVAL;
+        const double k = std::sqrt(k2);
+        double cos_s = std::sqrt(1.0 - sin_s * sin_s);
+        if (ring->alpha_c < 0.0)
+            cos_s = -cos_s;
+        out->n = n;
+        out->v_ratio = frac * k;
+        out->phase_n_rad = std::atan2(-sin_s / (k * n2), -cos_s / (k * (double)n));
+        return MBT_OK;
+    });
 }
 
 int mbt_set_harmonic_cavity(mbt_ctx *c, const mbt_hc *hc)
 {
-    if (!c)
-        return MBT_EINVAL;
-    mbt_hc h{};
-    if (hc) {
-        if (hc->n < 2 || !std::isfinite(hc->v_ratio) || hc->v_ratio < 0.0 ||
-            !std::isfinite(hc->phase_n_rad))
-            return fail(c, MBT_EINVAL, "bad harmonic cavity");
-        h = *hc;
-    }
-    double phi = 0.0;
-    int rc = solve_phi_s(c, hc != nullptr, h, &phi);
-    if (rc)
-        return rc;
-    c->hc_on = hc != nullptr;
-    c->hc = h;
-    c->phi_s = phi;
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        mbt_hc h{};
+        if (hc) {
+            if (hc->n < 2 || !std::isfinite(hc->v_ratio) || hc->v_ratio < 0.0 ||
+                !std::isfinite(hc->phase_n_rad))
+                return fail(c, MBT_EINVAL, "bad harmonic cavity");
+            h = *hc;
+        }
+        double phi = 0.0;
+        int rc = solve_phi_s(c, hc != nullptr, h, &phi);
+        if (rc)
+            return rc;
+        c->hc_on = hc != nullptr;
+        c->hc = h;
+        c->phi_s = phi;
+        return MBT_OK;
+    });
 }
 
 int mbt_set_fill(mbt_ctx *c, int32_t M, const int32_t *bucket, const double *current_A,
                  const int32_t *stream)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (c->bound)
-        return fail(c, MBT_ESTATE, "fill must be set before mbt_bind");
-    if (M < 1 || M > c->ring.harmonic || M > 65535 || !bucket || !current_A)
-        return fail(c, MBT_EINVAL, "need 1 <= M <= min(h, 65535) and non-null arrays");
-    for (int b = 0; b < M; ++b) {
-        if (bucket[b] < 0 || bucket[b] >= c->ring.harmonic || (b > 0 && bucket[b] <= bucket[b - 1]))
-            return fail(c, MBT_EINVAL, "buckets must be strictly increasing in [0, h)");
-        if (!(current_A[b] >= 0.0) || !std::isfinite(current_A[b]))
-            return fail(c, MBT_EINVAL, "bunch currents must be finite and >= 0");
-        if (stream && stream[b] < 0)
-            return fail(c, MBT_EINVAL, "stream ordinals must be >= 0");
-    }
-    c->M = M;
-    c->bucket.assign(bucket, bucket + M);
-    c->current.assign(current_A, current_A + M);
-    c->stream.resize(M);
-    for (int b = 0; b < M; ++b)
-        c->stream[b] = stream ? stream[b] : b;
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "fill must be set before mbt_bind");
+        if (M < 1 || M > c->ring.harmonic || M > 65535 || !bucket || !current_A)
+            return fail(c, MBT_EINVAL, "need 1 <= M <= min(h, 65535) and non-null arrays");
+        for (int b = 0; b < M; ++b) {
+            if (bucket[b] < 0 || bucket[b] >= c->ring.harmonic || (b > 0 && bucket[b] <= bucket[b - 1]))
+                return fail(c, MBT_EINVAL, "buckets must be strictly increasing in [0, h)");
+            if (!(current_A[b] >= 0.0) || !std::isfinite(current_A[b]))
+                return fail(c, MBT_EINVAL, "bunch currents must be finite and >= 0");
+            if (stream && stream[b] < 0)
+                return fail(c, MBT_EINVAL, "stream ordinals must be >= 0");
+        }
+        // built aside and swapped in, so a failed allocation leaves the
+        // previous fill in place
+        std::vector<int32_t> bk(bucket, bucket + M), st(M);
+        std::vector<double> cur(current_A, current_A + M);
+        for (int b = 0; b < M; ++b)
+            st[b] = stream ? stream[b] : b;
+        c->bucket.swap(bk);
+        c->current.swap(cur);
+        c->stream.swap(st);
+        c->M = M;
+        return MBT_OK;
+    });
 }
 
 int mbt_set_short_range(mbt_ctx *c, int32_t nres, const mbt_resonator *res, const mbt_grid *g)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (c->bound)
-        return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
-    if (!g) {
-        c->sr_on = false;
-        c->sr.clear();
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
+        if (!g) {
+            c->sr_on = false;
+            c->sr.clear();
+            return MBT_OK;
+        }
+        if (g->nbins < 1 || g->nbins > MBT_MAX_BINS || !std::isfinite(g->tau_min_s) ||
+            !std::isfinite(g->tau_max_s) || !(g->tau_min_s < g->tau_max_s))
+            return fail(c, MBT_EINVAL, "grid: need 1 <= nbins <= %d and tau_min < tau_max", MBT_MAX_BINS);
+        if (nres < 0 || nres > MBT_MAX_SHORT_RANGE || (nres > 0 && !res))
+            return fail(c, MBT_EINVAL, "need 0 <= nres <= %d", MBT_MAX_SHORT_RANGE);
+        for (int i = 0; i < nres; ++i)
+            if (!res_valid(res[i]))
+                return fail(c, MBT_EINVAL, "resonator %d: need Rs >= 0, Q > 0.5, fr > 0", i);
+        std::vector<Resonator> sr;
+        for (int i = 0; i < nres; ++i)
+            sr.push_back({res[i].rs_ohm, res[i].q, res[i].fr_Hz});
+        c->sr.swap(sr);
+        c->sr_on = true;
+        c->grid = *g;
         return MBT_OK;
-    }
-    if (g->nbins < 1 || g->nbins > MBT_MAX_BINS || !std::isfinite(g->tau_min_s) ||
-        !std::isfinite(g->tau_max_s) || !(g->tau_min_s < g->tau_max_s))
-        return fail(c, MBT_EINVAL, "grid: need 1 <= nbins <= %d and tau_min < tau_max", MBT_MAX_BINS);
-    if (nres < 0 || nres > MBT_MAX_SHORT_RANGE || (nres > 0 && !res))
-        return fail(c, MBT_EINVAL, "need 0 <= nres <= %d", MBT_MAX_SHORT_RANGE);
-    for (int i = 0; i < nres; ++i)
-        if (!res_valid(res[i]))
-            return fail(c, MBT_EINVAL, "resonator %d: need Rs >= 0, Q > 0.5, fr > 0", i);
-    c->sr_on = true;
-    c->grid = *g;
-    c->sr.clear();
-    for (int i = 0; i < nres; ++i)
-        c->sr.push_back({res[i].rs_ohm, res[i].q, res[i].fr_Hz});
-    return MBT_OK;
+    });
 }
 
 int mbt_set_long_range(mbt_ctx *c, int32_t nres, const mbt_resonator *res)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (c->bound)
-        return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
-    if (nres < 0 || nres > MBT_MAX_LONG_RANGE || (nres > 0 && !res))
-        return fail(c, MBT_EINVAL, "need 0 <= nres <= %d", MBT_MAX_LONG_RANGE);
-    for (int i = 0; i < nres; ++i)
-        if (!res_valid(res[i]))
-            return fail(c, MBT_EINVAL, "resonator %d: need Rs >= 0, Q > 0.5, fr > 0", i);
-    c->lr.clear();
-    for (int i = 0; i < nres; ++i)
-        c->lr.push_back({res[i].rs_ohm, res[i].q, res[i].fr_Hz});
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
+        if (nres < 0 || nres > MBT_MAX_LONG_RANGE || (nres > 0 && !res))
+            return fail(c, MBT_EINVAL, "need 0 <= nres <= %d", MBT_MAX_LONG_RANGE);
+        for (int i = 0; i < nres; ++i)
+            if (!res_valid(res[i]))
+                return fail(c, MBT_EINVAL, "resonator %d: need Rs >= 0, Q > 0.5, fr > 0", i);
+        std::vector<Resonator> lr;
+        for (int i = 0; i < nres; ++i)
+            lr.push_back({res[i].rs_ohm, res[i].q, res[i].fr_Hz});
+        c->lr.swap(lr);
+        return MBT_OK;
+    });
 }
 
 int mbt_set_resistive_wall(mbt_ctx *c, const mbt_resistive_wall *rw)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (c->bound)
-        return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
-    if (rw && !(std::isfinite(rw->radius_m) && rw->radius_m > 0.0 &&
-                std::isfinite(rw->conductivity_S_m) && rw->conductivity_S_m > 0.0 &&
-                std::isfinite(rw->length_m) && rw->length_m > 0.0))
-        return fail(c, MBT_EINVAL, "resistive wall: need radius, conductivity and length > 0");
-    c->rw_on = rw != nullptr;
-    if (rw)
-        c->rw = ResistiveWall{rw->radius_m, rw->conductivity_S_m, rw->length_m};
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
+        if (rw && !(std::isfinite(rw->radius_m) && rw->radius_m > 0.0 &&
+                    std::isfinite(rw->conductivity_S_m) && rw->conductivity_S_m > 0.0 &&
+                    std::isfinite(rw->length_m) && rw->length_m > 0.0))
+            return fail(c, MBT_EINVAL, "resistive wall: need radius, conductivity and length > 0");
+        c->rw_on = rw != nullptr;
+        if (rw)
+            c->rw = ResistiveWall{rw->radius_m, rw->conductivity_S_m, rw->length_m};
+        return MBT_OK;
+    });
 }
 
 int mbt_query_bytes(const mbt_ctx *c, int64_t N, size_t *state_bytes, size_t *work_bytes)
 {
-    if (!c || !state_bytes || !work_bytes)
-        return MBT_EINVAL;
-    if (c->M < 1)
-        return MBT_ESTATE;
-    if (N < 1 || N > ((int64_t)1 << 32))
-        return MBT_EINVAL;
-    Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
-    *state_bytes = L.state_bytes;
-    *work_bytes = L.total;
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!c || !state_bytes || !work_bytes)
+            return MBT_EINVAL;
+        if (c->M < 1)
+            return MBT_ESTATE;
+        if (N < 1 || N > ((int64_t)1 << 32))
+            return MBT_EINVAL;
+        Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
+        *state_bytes = L.state_bytes;
+        *work_bytes = L.total;
+        return MBT_OK;
+    });
 }
 
 int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_work,
              size_t work_bytes, void *hip_stream)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (c->M < 1)
-        return fail(c, MBT_ESTATE, "fill not set");
-    if (N < 1 || N > ((int64_t)1 << 32))
-        return fail(c, MBT_EINVAL, "N must be in [1, 2^32]");
-    if (!d_state || !d_work || ((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
-        return fail(c, MBT_EINVAL, "device buffers must be non-null and 256-byte aligned");
-    Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
-    if (state_bytes < L.state_bytes || work_bytes < L.total)
-        return fail(c, MBT_ENOSPC, "need %zu state and %zu workspace bytes", L.state_bytes, L.total);
-    release_binding(c);
-    c->L = L;
-    c->N = N;
-    c->tau = reinterpret_cast<double *>(d_state);
-    c->delta = c->tau + (size_t)c->M * L.ld;
-    c->work = reinterpret_cast<unsigned char *>(d_work);
-    c->stream_h = reinterpret_cast<hipStream_t>(hip_stream);
-    HIPCHK(c, hipGetDevice(&c->device));
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->M < 1)
+            return fail(c, MBT_ESTATE, "fill not set");
+        if (N < 1 || N > ((int64_t)1 << 32))
+            return fail(c, MBT_EINVAL, "N must be in [1, 2^32]");
+        if (!d_state || !d_work || ((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
+            return fail(c, MBT_EINVAL, "device buffers must be non-null and 256-byte aligned");
+        Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
+        if (state_bytes < L.state_bytes || work_bytes < L.total)
+            return fail(c, MBT_ENOSPC, "need %zu state and %zu workspace bytes", L.state_bytes, L.total);
+        release_binding(c);
+        c->L = L;
+        c->N = N;
+        c->tau = reinterpret_cast<double *>(d_state);
+        c->delta = c->tau + (size_t)c->M * L.ld;
+        c->work = reinterpret_cast<unsigned char *>(d_work);
+        c->stream_h = reinterpret_cast<hipStream_t>(hip_stream);
+        HIPCHK(c, hipGetDevice(&c->device));
 
-    const int M = c->M, nb = c->nbins(), nbx = std::max(nb, 1), nlr = c->nlr();
-    // Host-side tables.
-    std::vector<double> W((size_t)nbx, 0.0);
-    if (c->sr_on) {
-        // Sum of all resonators sampled at bin distances (Sec. 2.3); the
-        // long-range ones contribute their same-bunch, same-turn part here.
-        const double dt = (c->grid.tau_max_s - c->grid.tau_min_s) / (double)nb;
-        std::vector<Resonator> all = c->sr;
-        all.insert(all.end(), c->lr.begin(), c->lr.end());
-        for (const Resonator &r : all) {
-            W[0] += 0.5 * r.wake(0.0);
-            for (int k = 1; k < nb; ++k)
-                W[k] += r.wake((double)k * dt);
-        }
-        if (c->rw_on) {
-            std::vector<double> gx, gw;
-            gauss_legendre(24, gx, gw);
-            W[0] += 0.5 * rw_wake(c->rw, 0.0, gx, gw);
-            for (int k = 1; k < nb; ++k)
-                W[k] += rw_wake(c->rw, (double)k * dt, gx, gw);
-        }
-    }
-    std::vector<double> qpp(M), gap((size_t)std::max(nlr, 1) * M * 2, 0.0),
-        qc((size_t)std::max(nlr, 1) * M * 2, 0.0);
-    std::vector<uint32_t> strm(M);
-    for (int b = 0; b < M; ++b) {
-        qpp[b] = c->current[b] * c->T0 / (double)N;
-        strm[b] = (uint32_t)c->stream[b];
-    }
-    for (int r = 0; r < nlr; ++r) {
-        const double a = c->lr[r].alpha(), wb = c->lr[r].wbar();
-        // W(t) = Re[c_r exp((-alpha + i wbar) t)], c_r = 2 alpha Rs (1 + i alpha/wbar)
-        const double cr = 2.0 * a * c->lr[r].rs, ci = 2.0 * a * c->lr[r].rs * (a / wb);
-        for (int b = 0; b < M; ++b) {
-            const int g = (b == 0) ? (c->ring.harmonic - c->bucket[M - 1] + c->bucket[0])
-                                   : (c->bucket[b] - c->bucket[b - 1]);
-            const double t = (double)g * c->T_rf;
-            const double e = std::exp(-a * t);
-            const size_t ix = ((size_t)r * M + b) * 2;
-            gap[ix] = e * std::cos(wb * t);
-            gap[ix + 1] = e * std::sin(wb * t);
-            qc[ix] = qpp[b] * cr;
-            qc[ix + 1] = qpp[b] * ci;
-        }
-    }
-    std::vector<Item> pitems, citems, witems;
-    pitems.reserve((size_t)M * L.ntiles);
-    citems.reserve((size_t)M * L.nchunks);
-    push_items(c, 0, pitems);
-    prep_items(c, 0, citems);
-    wake_items(c, 0, witems);
-    // Matrix-core tables of the wake: W / s with s a power of two near max |W|,
-    // as FP32 and as three BF16 terms (each the BF16 nearest to what the
-    // previous ones leave).  Bin counts stay below 2^(8 count_parts).
-    std::vector<uint16_t> wbf((size_t)3 * nbx, 0);
-    std::vector<float> wf((size_t)nbx, 0.f);
-    {
-        double wmax = 0.0;
-        for (double v : W)
-            wmax = std::max(wmax, std::fabs(v));
-        int e = 0;
-        if (wmax > 0.0)
-            std::frexp(wmax, &e);  // wmax = f 2^e, f in [1/2, 1)
-        c->wake_scale = wmax > 0.0 ? std::ldexp(1.0, e) : 1.0;
-        for (int k = 0; k < nbx; ++k) {
-            double rest = W[k] / c->wake_scale;
-            wf[k] = (float)rest;
-            for (int q = 0; q < 3; ++q) {
-                const uint16_t h = bf16_nearest(rest);
-                wbf[(size_t)q * nbx + k] = h;
-                rest -= bf16_value(h);
+        const int M = c->M, nb = c->nbins(), nbx = std::max(nb, 1), nlr = c->nlr();
+        // Host-side tables.
+        std::vector<double> W((size_t)nbx, 0.0);
+        if (c->sr_on) {
+            // Sum of all resonators sampled at bin distances (Sec. 2.3); the
+            // long-range ones contribute their same-bunch, same-turn part here.
+            const double dt = (c->grid.tau_max_s - c->grid.tau_min_s) / (double)nb;
+            std::vector<Resonator> all = c->sr;
+            all.insert(all.end(), c->lr.begin(), c->lr.end());
+            for (const Resonator &r : all) {
+                W[0] += 0.5 * r.wake(0.0);
+                for (int k = 1; k < nb; ++k)
+                    W[k] += r.wake((double)k * dt);
+            }
+            if (c->rw_on) {
+                std::vector<double> gx, gw;
+                gauss_legendre(24, gx, gw);
+                W[0] += 0.5 * rw_wake(c->rw, 0.0, gx, gw);
+                for (int k = 1; k < nb; ++k)
+                    W[k] += rw_wake(c->rw, (double)k * dt, gx, gw);
             }
         }
-        c->count_parts = 1;
-        while (c->count_parts < 4 && (double)N >= std::ldexp(1.0, 8 * c->count_parts))
-            ++c->count_parts;
-    }
-    HIPCHK(c, hipMemsetAsync(c->work, 0, L.total, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<double>(L.W), W.data(), W.size() * sizeof(double),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<double>(L.qpp), qpp.data(), qpp.size() * sizeof(double),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<double>(L.gap), gap.data(), gap.size() * sizeof(double),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<double>(L.qc), qc.data(), qc.size() * sizeof(double),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<uint32_t>(L.stream), strm.data(), strm.size() * sizeof(uint32_t),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_push), pitems.data(), pitems.size() * sizeof(Item),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_prep), citems.data(), citems.size() * sizeof(Item),
-                             hipMemcpyHostToDevice, c->stream_h));
-    if (!witems.empty())
-        HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_wake), witems.data(), witems.size() * sizeof(Item),
+        std::vector<double> qpp(M), gap((size_t)std::max(nlr, 1) * M * 2, 0.0),
+            qc((size_t)std::max(nlr, 1) * M * 2, 0.0);
+        std::vector<uint32_t> strm(M);
+        for (int b = 0; b < M; ++b) {
+            qpp[b] = c->current[b] * c->T0 / (double)N;
+            strm[b] = (uint32_t)c->stream[b];
+        }
+        for (int r = 0; r < nlr; ++r) {
+            const double a = c->lr[r].alpha(), wb = c->lr[r].wbar();
+            // W(t) = Re[c_r exp((-alpha + i wbar) t)], c_r = 2 alpha Rs (1 + i alpha/wbar)
+            const double cr = 2.0 * a * c->lr[r].rs, ci = 2.0 * a * c->lr[r].rs * (a / wb);
+            for (int b = 0; b < M; ++b) {
+                const int g = (b == 0) ? (c->ring.harmonic - c->bucket[M - 1] + c->bucket[0])
+                                       : (c->bucket[b] - c->bucket[b - 1]);
+                const double t = (double)g * c->T_rf;
+                const double e = std::exp(-a * t);
+                const size_t ix = ((size_t)r * M + b) * 2;
+                gap[ix] = e * std::cos(wb * t);
+                gap[ix + 1] = e * std::sin(wb * t);
+                qc[ix] = qpp[b] * cr;
+                qc[ix + 1] = qpp[b] * ci;
+            }
+        }
+        std::vector<Item> pitems, citems, witems;
+        pitems.reserve((size_t)M * L.ntiles);
+        citems.reserve((size_t)M * L.nchunks);
+        push_items(c, 0, pitems);
+        prep_items(c, 0, citems);
+        wake_items(c, 0, witems);
+        // Matrix-core tables of the wake: W / s with s a power of two near max |W|,
+        // as FP32 and as three BF16 terms (each the BF16 nearest to what the
+        // previous ones leave).  Bin counts stay below 2^(8 count_parts).
+        std::vector<uint16_t> wbf((size_t)3 * nbx, 0);
+        std::vector<float> wf((size_t)nbx, 0.f);
+        {
+            double wmax = 0.0;
+            for (double v : W)
+                wmax = std::max(wmax, std::fabs(v));
+            int e = 0;
+            if (wmax > 0.0)
+                std::frexp(wmax, &e);  // wmax = f 2^e, f in [1/2, 1)
+            c->wake_scale = wmax > 0.0 ? std::ldexp(1.0, e) : 1.0;
+            for (int k = 0; k < nbx; ++k) {
+                double rest = W[k] / c->wake_scale;
+                wf[k] = (float)rest;
+                for (int q = 0; q < 3; ++q) {
+                    const uint16_t h = bf16_nearest(rest);
+                    wbf[(size_t)q * nbx + k] = h;
+                    rest -= bf16_value(h);
+                }
+            }
+            c->count_parts = 1;
+            while (c->count_parts < 4 && (double)N >= std::ldexp(1.0, 8 * c->count_parts))
+                ++c->count_parts;
+        }
+        HIPCHK(c, hipMemsetAsync(c->work, 0, L.total, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<double>(L.W), W.data(), W.size() * sizeof(double),
                                  hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<uint16_t>(L.Wbf), wbf.data(), wbf.size() * sizeof(uint16_t),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(c->w<float>(L.Wf32), wf.data(), wf.size() * sizeof(float),
-                             hipMemcpyHostToDevice, c->stream_h));
-    HIPCHK(c, hipMemsetAsync(d_state, 0, L.state_bytes, c->stream_h));
-    HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    HIPCHK(c, hipHostMalloc((void **)&c->mirror, sizeof(Mirror), hipHostMallocDefault));
-    int rc = ring_alloc(c, c->mom, c->w<double>(L.mom), (size_t)M * sizeof(mbt_moments), L.mom_slots);
-    if (!rc)
-        rc = ring_alloc(c, c->prof, c->w<uint32_t>(L.prof), (size_t)M * nbx * sizeof(uint32_t),
-                        L.prof_slots);
-    if (rc) {
-        release_binding(c);
-        return rc;
-    }
-    if (c->nsub == 0 || push_lds_bytes(nb, c->nsub) > kLdsLimit)
-        c->nsub = default_nsub(nb);
-    if (nb == 0)
-        c->nsub = 0;
-    c->bound = true;
-    c->have_particles = false;
-    c->dirty = true;
-    c->turn = 0;
-    return MBT_OK;
+        HIPCHK(c, hipMemcpyAsync(c->w<double>(L.qpp), qpp.data(), qpp.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<double>(L.gap), gap.data(), gap.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<double>(L.qc), qc.data(), qc.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<uint32_t>(L.stream), strm.data(), strm.size() * sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_push), pitems.data(), pitems.size() * sizeof(Item),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_prep), citems.data(), citems.size() * sizeof(Item),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        if (!witems.empty())
+            HIPCHK(c, hipMemcpyAsync(c->w<Item>(L.items_wake), witems.data(), witems.size() * sizeof(Item),
+                                     hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<uint16_t>(L.Wbf), wbf.data(), wbf.size() * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->w<float>(L.Wf32), wf.data(), wf.size() * sizeof(float),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipMemsetAsync(d_state, 0, L.state_bytes, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        HIPCHK(c, hipHostMalloc((void **)&c->mirror, sizeof(Mirror), hipHostMallocDefault));
+        int rc = ring_alloc(c, c->mom, c->w<double>(L.mom), (size_t)M * sizeof(mbt_moments), L.mom_slots);
+        if (!rc)
+            rc = ring_alloc(c, c->prof, c->w<uint32_t>(L.prof), (size_t)M * nbx * sizeof(uint32_t),
+                            L.prof_slots);
+        if (rc) {
+            release_binding(c);
+            return rc;
+        }
+        if (c->nsub == 0 || push_lds_bytes(nb, c->nsub) > kLdsLimit)
+            c->nsub = default_nsub(nb);
+        if (nb == 0)
+            c->nsub = 0;
+        c->bound = true;
+        c->have_particles = false;
+        c->dirty = true;
+        c->turn = 0;
+        return MBT_OK;
+    });
 }
 
 int mbt_init_gaussian(mbt_ctx *c, double sigma_tau_s, double sigma_delta, uint64_t seed)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (!(sigma_tau_s >= 0.0) || !(sigma_delta >= 0.0) || !std::isfinite(sigma_tau_s) ||
-        !std::isfinite(sigma_delta))
-        return fail(c, MBT_EINVAL, "sigmas must be finite and >= 0");
-    HIPCHK(c, launch_init_gauss(c->tau, c->delta, c->L.ld, c->N, c->M,
-                                c->w<uint32_t>(c->L.stream), sigma_tau_s, sigma_delta,
-                                (uint32_t)seed, (uint32_t)(seed >> 32), c->stream_h));
-    HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.phasor), 0,
-                             (size_t)std::max(c->nlr(), 1) * 2 * sizeof(double), c->stream_h));
-    c->seed = seed;
-    c->turn = 0;
-    c->have_particles = true;
-    c->dirty = true;
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!(sigma_tau_s >= 0.0) || !(sigma_delta >= 0.0) || !std::isfinite(sigma_tau_s) ||
+            !std::isfinite(sigma_delta))
+            return fail(c, MBT_EINVAL, "sigmas must be finite and >= 0");
+        HIPCHK(c, launch_init_gauss(c->tau, c->delta, c->L.ld, c->N, c->M,
+                                    c->w<uint32_t>(c->L.stream), sigma_tau_s, sigma_delta,
+                                    (uint32_t)seed, (uint32_t)(seed >> 32), c->stream_h));
+        HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.phasor), 0,
+                                 (size_t)std::max(c->nlr(), 1) * 2 * sizeof(double), c->stream_h));
+        c->seed = seed;
+        c->turn = 0;
+        c->have_particles = true;
+        c->dirty = true;
+        return MBT_OK;
+    });
 }
 
 int mbt_set_particles(mbt_ctx *c, int32_t bunch, const double *tau, const double *delta,
                       int32_t where)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (bunch < 0 || bunch >= c->M || !tau || !delta || (where != MBT_HOST && where != MBT_DEVICE))
-        return fail(c, MBT_EINVAL, "bad bunch index, null array or location");
-    const size_t bytes = (size_t)c->N * sizeof(double);
-    const hipMemcpyKind kind = where == MBT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    double *dt = c->tau + (size_t)bunch * c->L.ld, *dd = c->delta + (size_t)bunch * c->L.ld;
-    HIPCHK(c, hipMemcpyAsync(dt, tau, bytes, kind, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(dd, delta, bytes, kind, c->stream_h));
-    if (where == MBT_HOST)
-        HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    c->have_particles = true;
-    c->dirty = true;
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (bunch < 0 || bunch >= c->M || !tau || !delta || (where != MBT_HOST && where != MBT_DEVICE))
+            return fail(c, MBT_EINVAL, "bad bunch index, null array or location");
+        const size_t bytes = (size_t)c->N * sizeof(double);
+        const hipMemcpyKind kind = where == MBT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        double *dt = c->tau + (size_t)bunch * c->L.ld, *dd = c->delta + (size_t)bunch * c->L.ld;
+        HIPCHK(c, hipMemcpyAsync(dt, tau, bytes, kind, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(dd, delta, bytes, kind, c->stream_h));
+        if (where == MBT_HOST)
+            HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        c->have_particles = true;
+        c->dirty = true;
+        return MBT_OK;
+    });
 }
 
 int mbt_get_particles(mbt_ctx *c, int32_t bunch, double *tau, double *delta, int32_t where)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (bunch < 0 || bunch >= c->M || !tau || !delta || (where != MBT_HOST && where != MBT_DEVICE))
-        return fail(c, MBT_EINVAL, "bad bunch index, null array or location");
-    const size_t bytes = (size_t)c->N * sizeof(double);
-    const hipMemcpyKind kind = where == MBT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-    HIPCHK(c, hipMemcpyAsync(tau, c->tau + (size_t)bunch * c->L.ld, bytes, kind, c->stream_h));
-    HIPCHK(c, hipMemcpyAsync(delta, c->delta + (size_t)bunch * c->L.ld, bytes, kind, c->stream_h));
-    HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (bunch < 0 || bunch >= c->M || !tau || !delta || (where != MBT_HOST && where != MBT_DEVICE))
+            return fail(c, MBT_EINVAL, "bad bunch index, null array or location");
+        const size_t bytes = (size_t)c->N * sizeof(double);
+        const hipMemcpyKind kind = where == MBT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        HIPCHK(c, hipMemcpyAsync(tau, c->tau + (size_t)bunch * c->L.ld, bytes, kind, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(delta, c->delta + (size_t)bunch * c->L.ld, bytes, kind, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        return MBT_OK;
+    });
 }
 
 int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, int32_t stride)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (!c->have_particles)
-        return fail(c, MBT_ESTATE, "particles not initialised");
-    if (nturns < 0 || nturns > INT32_MAX || c->turn + nturns > ((int64_t)1 << 32))
-        return fail(c, MBT_EINVAL, "need nturns < 2^31 and the turn counter below 2^32");
-    if (counts && (!c->sr_on || stride < 1))
-        return fail(c, MBT_EINVAL, "profiles need a grid and stride >= 1");
-    if (nturns == 0)
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!c->have_particles)
+            return fail(c, MBT_ESTATE, "particles not initialised");
+        if (nturns < 0 || nturns > INT32_MAX || c->turn + nturns > ((int64_t)1 << 32))
+            return fail(c, MBT_EINVAL, "need nturns < 2^31 and the turn counter below 2^32");
+        if (counts && (!c->sr_on || stride < 1))
+            return fail(c, MBT_EINVAL, "profiles need a grid and stride >= 1");
+        if (nturns == 0)
+            return MBT_OK;
+        hipStream_t s = c->stream_h;
+        rc = begin_call(c, counts ? stride : 0, s);
+        if (rc)
+            return rc;
+        ring_start(c->mom, out);
+        ring_start(c->prof, counts);
+        const Engine e = single_engine(c);
+        for (int64_t t = 0; t < nturns; ++t) {
+            const bool timed = c->timer.every > 0 && (t % c->timer.every) == 0;
+            HIPCHK(c, ring_advance(c->mom, 1, s));
+            HIPCHK(c, ring_advance(c->prof, profile_rows(t, 1, stride), s));
+            HIPCHK(c, enqueue_turn(e, (int)(t & 1), s, timed ? &c->timer : nullptr));
+        }
+        c->turn += nturns;
+        HIPCHK(c, ring_flush(c->mom, s));
+        HIPCHK(c, ring_flush(c->prof, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, ring_land(c->mom));
+        HIPCHK(c, ring_land(c->prof));
+        HIPCHK(c, timer_collect(c->timer));
+        uint32_t status = 0;
+        HIPCHK(c, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
+        if (status) {
+            HIPCHK(c, hipMemset(c->w<uint32_t>(c->L.status), 0, sizeof status));
+            return fail(c, MBT_ENUMERIC, "non-finite bunch moment during turns %lld..%lld",
+                        (long long)(c->turn - nturns), (long long)(c->turn - 1));
+        }
         return MBT_OK;
-    hipStream_t s = c->stream_h;
-    rc = begin_call(c, counts ? stride : 0, s);
-    if (rc)
-        return rc;
-    ring_start(c->mom, out);
-    ring_start(c->prof, counts);
-    const Engine e = single_engine(c);
-    for (int64_t t = 0; t < nturns; ++t) {
-        const bool timed = c->timer.every > 0 && (t % c->timer.every) == 0;
-        HIPCHK(c, ring_advance(c->mom, 1, s));
-        HIPCHK(c, ring_advance(c->prof, profile_rows(t, 1, stride), s));
-        HIPCHK(c, enqueue_turn(e, (int)(t & 1), s, timed ? &c->timer : nullptr));
-    }
-    c->turn += nturns;
-    HIPCHK(c, ring_flush(c->mom, s));
-    HIPCHK(c, ring_flush(c->prof, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    HIPCHK(c, ring_land(c->mom));
-    HIPCHK(c, ring_land(c->prof));
-    HIPCHK(c, timer_collect(c->timer));
-    uint32_t status = 0;
-    HIPCHK(c, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
-    if (status) {
-        HIPCHK(c, hipMemset(c->w<uint32_t>(c->L.status), 0, sizeof status));
-        return fail(c, MBT_ENUMERIC, "non-finite bunch moment during turns %lld..%lld",
-                    (long long)(c->turn - nturns), (long long)(c->turn - 1));
-    }
-    return MBT_OK;
+    });
 }
 
 int mbt_profile(mbt_ctx *c, uint32_t *counts)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (!counts || !c->sr_on)
-        return fail(c, MBT_EINVAL, "need a grid and an output array");
-    if (!c->have_particles)
-        return fail(c, MBT_ESTATE, "particles not initialised");
-    rc = begin_call(c, 0, c->stream_h);
-    if (rc)
-        return rc;
-    // the prep leaves the present state's histogram in counts[turn & 1]
-    const size_t bytes = (size_t)c->M * c->nbins() * sizeof(uint32_t);
-    HIPCHK(c, hipMemcpyAsync(counts, c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * c->nbins(),
-                             bytes, hipMemcpyDeviceToHost, c->stream_h));
-    HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!counts || !c->sr_on)
+            return fail(c, MBT_EINVAL, "need a grid and an output array");
+        if (!c->have_particles)
+            return fail(c, MBT_ESTATE, "particles not initialised");
+        rc = begin_call(c, 0, c->stream_h);
+        if (rc)
+            return rc;
+        // the prep leaves the present state's histogram in counts[turn & 1]
+        const size_t bytes = (size_t)c->M * c->nbins() * sizeof(uint32_t);
+        HIPCHK(c, hipMemcpyAsync(counts, c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * c->nbins(),
+                                 bytes, hipMemcpyDeviceToHost, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        return MBT_OK;
+    });
 }
 
 int mbt_wake_potential(mbt_ctx *c, double *V)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (!V || !c->sr_on)
-        return fail(c, MBT_EINVAL, "need a grid and an output array");
-    if (!c->have_particles)
-        return fail(c, MBT_ESTATE, "particles not initialised");
-    rc = begin_call(c, 0, c->stream_h);
-    if (rc)
-        return rc;
-    HIPCHK(c, hipMemcpyAsync(V, c->w<double>(c->L.V), (size_t)c->M * c->nbins() * sizeof(double),
-                             hipMemcpyDeviceToHost, c->stream_h));
-    HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!V || !c->sr_on)
+            return fail(c, MBT_EINVAL, "need a grid and an output array");
+        if (!c->have_particles)
+            return fail(c, MBT_ESTATE, "particles not initialised");
+        rc = begin_call(c, 0, c->stream_h);
+        if (rc)
+            return rc;
+        HIPCHK(c, hipMemcpyAsync(V, c->w<double>(c->L.V), (size_t)c->M * c->nbins() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        return MBT_OK;
+    });
 }
 
 int mbt_wake_table(const mbt_ctx *c, double *W)
 {
-    if (!c || !W)
-        return MBT_EINVAL;
-    if (!c->bound || !c->sr_on)
-        return MBT_ESTATE;
-    if (hipMemcpy(W, c->w<double>(c->L.W), (size_t)c->nbins() * sizeof(double),
-                  hipMemcpyDeviceToHost) != hipSuccess)
-        return MBT_EDEVICE;
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!c || !W)
+            return MBT_EINVAL;
+        if (!c->bound || !c->sr_on)
+            return MBT_ESTATE;
+        if (hipMemcpy(W, c->w<double>(c->L.W), (size_t)c->nbins() * sizeof(double),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return MBT_EDEVICE;
+        return MBT_OK;
+    });
 }
 
 int mbt_get_state(mbt_ctx *c, int64_t *turn, uint64_t *seed, double *phasors)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (turn)
-        *turn = c->turn;
-    if (seed)
-        *seed = c->seed;
-    if (phasors && c->nlr() > 0) {
-        HIPCHK(c, hipMemcpyAsync(phasors, c->w<double>(c->L.phasor), (size_t)c->nlr() * 2 * sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream_h));
-        HIPCHK(c, hipStreamSynchronize(c->stream_h));
-    }
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (turn)
+            *turn = c->turn;
+        if (seed)
+            *seed = c->seed;
+        if (phasors && c->nlr() > 0) {
+            HIPCHK(c, hipMemcpyAsync(phasors, c->w<double>(c->L.phasor), (size_t)c->nlr() * 2 * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream_h));
+            HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        }
+        return MBT_OK;
+    });
 }
 
 int mbt_set_state(mbt_ctx *c, int64_t turn, uint64_t seed, const double *phasors)
 {
-    int rc = need_bound(c);
-    if (rc)
-        return rc;
-    if (turn < 0 || turn > ((int64_t)1 << 32))
-        return fail(c, MBT_EINVAL, "turn out of range");
-    if (c->nlr() > 0) {
-        const size_t bytes = (size_t)c->nlr() * 2 * sizeof(double);
-        if (phasors) {
-            HIPCHK(c, hipMemcpyAsync(c->w<double>(c->L.phasor), phasors, bytes, hipMemcpyHostToDevice,
-                                     c->stream_h));
-            HIPCHK(c, hipStreamSynchronize(c->stream_h));
-        } else {
-            HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.phasor), 0, bytes, c->stream_h));
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (turn < 0 || turn > ((int64_t)1 << 32))
+            return fail(c, MBT_EINVAL, "turn out of range");
+        if (c->nlr() > 0) {
+            const size_t bytes = (size_t)c->nlr() * 2 * sizeof(double);
+            if (phasors) {
+                HIPCHK(c, hipMemcpyAsync(c->w<double>(c->L.phasor), phasors, bytes, hipMemcpyHostToDevice,
+                                         c->stream_h));
+                HIPCHK(c, hipStreamSynchronize(c->stream_h));
+            } else {
+                HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.phasor), 0, bytes, c->stream_h));
+            }
         }
-    }
-    c->turn = turn;
-    c->seed = seed;
-    c->dirty = true;
-    return MBT_OK;
+        c->turn = turn;
+        c->seed = seed;
+        c->dirty = true;
+        return MBT_OK;
+    });
 }
 
 int mbt_set_timing(mbt_ctx *c, int32_t every)
 {
-    if (!c || every < 0)
-        return MBT_EINVAL;
-    HIPCHK(c, timer_set(c->timer, every));
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c || every < 0)
+            return MBT_EINVAL;
+        HIPCHK(c, timer_set(c->timer, every));
+        return MBT_OK;
+    });
 }
 
 int mbt_get_timing(const mbt_ctx *c, double *push_ms, int64_t *push_launches, double *prep_ms,
                    int64_t *prep_launches)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (push_ms)
-        *push_ms = c->timer.ms[0];
-    if (push_launches)
-        *push_launches = c->timer.launches[0];
-    if (prep_ms)
-        *prep_ms = c->timer.ms[1];
-    if (prep_launches)
-        *prep_launches = c->timer.launches[1];
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (push_ms)
+            *push_ms = c->timer.ms[0];
+        if (push_launches)
+            *push_launches = c->timer.launches[0];
+        if (prep_ms)
+            *prep_ms = c->timer.ms[1];
+        if (prep_launches)
+            *prep_launches = c->timer.launches[1];
+        return MBT_OK;
+    });
 }
 
 int mbt_set_wake_precision(mbt_ctx *c, int32_t mode)
 {
-    if (!c)
-        return MBT_EINVAL;
-    if (mode < MBT_WAKE_FP64 || mode > MBT_WAKE_BF16X3)
-        return fail(c, MBT_EINVAL, "unknown wake precision %d", mode);
-    if (mode != c->wake_mode)
-        c->dirty = true;  // the stored wake potential used the other arithmetic
-    c->wake_mode = mode;
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (mode < MBT_WAKE_FP64 || mode > MBT_WAKE_BF16X3)
+            return fail(c, MBT_EINVAL, "unknown wake precision %d", mode);
+        if (mode != c->wake_mode)
+            c->dirty = true;  // the stored wake potential used the other arithmetic
+        c->wake_mode = mode;
+        return MBT_OK;
+    });
 }
 
 int mbt_set_launch(mbt_ctx *c, int32_t nsub, int32_t push_grid)
 {
-    if (!c)
-        return MBT_EINVAL;
-    const int nb = c->nbins();
-    if (push_grid < 0 || nsub < 0 || (nb > 0 && nsub > 0 && push_lds_bytes(nb, nsub) > kLdsLimit))
-        return fail(c, MBT_EINVAL, "need push_grid >= 0 and 0 <= nsub with the LDS image <= %zu bytes",
-                    kLdsLimit);
-    c->nsub = nb == 0 ? 0 : (nsub == 0 ? default_nsub(nb) : nsub);
-    c->push_grid = push_grid;
-    return MBT_OK;
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        const int nb = c->nbins();
+        if (push_grid < 0 || nsub < 0 || (nb > 0 && nsub > 0 && push_lds_bytes(nb, nsub) > kLdsLimit))
+            return fail(c, MBT_EINVAL, "need push_grid >= 0 and 0 <= nsub with the LDS image <= %zu bytes",
+                        kLdsLimit);
+        c->nsub = nb == 0 ? 0 : (nsub == 0 ? default_nsub(nb) : nsub);
+        c->push_grid = push_grid;
+        return MBT_OK;
+    });
 }
 
 int mbt_philox4x32_10(int64_t n, const uint32_t *ctr, uint32_t key0, uint32_t key1, uint32_t *out,
                       void *hip_stream)
 {
-    if (n < 0 || (n > 0 && (!ctr || !out)))
-        return MBT_EINVAL;
-    if (launch_philox(n, ctr, key0, key1, out, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
-        return MBT_EDEVICE;
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (n < 0 || (n > 0 && (!ctr || !out)))
+            return MBT_EINVAL;
+        if (launch_philox(n, ctr, key0, key1, out, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+            return MBT_EDEVICE;
+        return MBT_OK;
+    });
 }
 
 int mbt_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream)
 {
-    if (bytes < 0 || (bytes % 16) != 0)
-        return MBT_EINVAL;
-    if (bytes == 0)
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (bytes < 0 || (bytes % 16) != 0)
+            return MBT_EINVAL;
+        if (bytes == 0)
+            return MBT_OK;
+        if (!src || !dst || (reinterpret_cast<uintptr_t>(src) & 15u) ||
+            (reinterpret_cast<uintptr_t>(dst) & 15u))
+            return MBT_EINVAL;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+        if (a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
+            return MBT_EINVAL;  // overlapping ranges
+        if (launch_stream_copy(src, dst, bytes, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+            return MBT_EDEVICE;
         return MBT_OK;
-    if (!src || !dst || (reinterpret_cast<uintptr_t>(src) & 15u) ||
-        (reinterpret_cast<uintptr_t>(dst) & 15u))
-        return MBT_EINVAL;
-    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
-    if (a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
-        return MBT_EINVAL;  // overlapping ranges
-    if (launch_stream_copy(src, dst, bytes, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
-        return MBT_EDEVICE;
-    return MBT_OK;
+    });
 }
 
 }  // extern "C"
@@ -1577,7 +1656,11 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
                 if (cand[gi][d].nsub == dsub && cand[gi][d].grid == 0 &&
                     best[gi][k] > 0.98f * best[gi][d])
                     k = d;
-            g_tune_cache[tune_key(B->eng.groups[gi])] = cand[gi][k];
+            try {
+                g_tune_cache[tune_key(B->eng.groups[gi])] = cand[gi][k];
+            } catch (const std::bad_alloc &) {
+                // the tuned turns are already tracked: keep the choice, uncached
+            }
             apply_choice(B, (int)gi, cand[gi][k]);
         }
     }
@@ -1616,276 +1699,290 @@ extern "C" {
 
 int mbt_batch_query_bytes(mbt_ctx *const *jobs, int32_t njobs, size_t *work_bytes)
 {
-    if (!jobs || njobs < 1 || njobs > 65535 || !work_bytes)
-        return MBT_EINVAL;
-    for (int j = 0; j < njobs; ++j)
-        if (!jobs[j] || !jobs[j]->bound)
-            return MBT_ESTATE;
-    size_t a, b, w;
-    *work_bytes = batch_layout(jobs, njobs, &a, &b, &w);
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!jobs || njobs < 1 || njobs > 65535 || !work_bytes)
+            return MBT_EINVAL;
+        for (int j = 0; j < njobs; ++j)
+            if (!jobs[j] || !jobs[j]->bound)
+                return MBT_ESTATE;
+        size_t a, b, w;
+        *work_bytes = batch_layout(jobs, njobs, &a, &b, &w);
+        return MBT_OK;
+    });
 }
 
 int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t work_bytes,
                      void *hip_stream, mbt_batch **out)
 {
-    if (!out)
-        return MBT_EINVAL;
-    *out = nullptr;
-    size_t need = 0;
-    int rc = mbt_batch_query_bytes(jobs, njobs, &need);
-    if (rc)
-        return rc;
-    if (!d_work || ((uintptr_t)d_work & 255))
-        return MBT_EINVAL;
-    if (work_bytes < need)
-        return MBT_ENOSPC;
-    for (int j = 0; j < njobs; ++j) {
-        if (jobs[j]->device != jobs[0]->device)
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!out)
             return MBT_EINVAL;
-        for (int k = 0; k < j; ++k)
-            if (jobs[k] == jobs[j])
-                return MBT_EINVAL;
-    }
-    mbt_batch *B = new (std::nothrow) mbt_batch();
-    if (!B)
-        return MBT_ENOMEM;
-    B->jobs.assign(jobs, jobs + njobs);
-    B->work = reinterpret_cast<unsigned char *>(d_work);
-    B->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep, &B->off_wake);
-    // items grouped by long-range count, jobs in the order given
-    std::vector<Item> pitems, citems;
-    Engine &e = B->eng;
-    for (int nlr = 0; nlr <= kMaxLR; ++nlr) {
-        Group g;
-        g.item0 = (int)pitems.size();
-        g.nlr = nlr;
-        g.map = -1;
+        *out = nullptr;
+        size_t need = 0;
+        int rc = mbt_batch_query_bytes(jobs, njobs, &need);
+        if (rc)
+            return rc;
+        if (!d_work || ((uintptr_t)d_work & 255))
+            return MBT_EINVAL;
+        if (work_bytes < need)
+            return MBT_ENOSPC;
         for (int j = 0; j < njobs; ++j) {
-            mbt_ctx *c = jobs[j];
-            if (c->nlr() != nlr)
-                continue;
-            push_items(c, j, pitems);
-            g.nbins_max = std::max(g.nbins_max, c->nbins());
-            g.nsub_max = std::max(g.nsub_max, c->nsub);
-            const int k = map_kind(c);
-            g.map = (g.map < 0 || g.map == k) ? k : kMapGeneric;
+            if (jobs[j]->device != jobs[0]->device)
+                return MBT_EINVAL;
+            for (int k = 0; k < j; ++k)
+                if (jobs[k] == jobs[j])
+                    return MBT_EINVAL;
         }
-        if (g.map < 0)
-            g.map = kMapGeneric;
-        g.nitems = (int)pitems.size() - g.item0;
-        if (g.nitems > 0)
-            e.groups.push_back(g);
-    }
-    for (int j = 0; j < njobs; ++j) {
-        if (!mfma_wake(jobs[j]))
-            prep_items(jobs[j], j, citems);  // k_wake does a matrix-core job's prep
-        e.nlr_max = std::max(e.nlr_max, jobs[j]->nlr());
-        e.nbins_max = std::max(e.nbins_max, jobs[j]->nbins());
-        B->wake_modes.push_back(jobs[j]->wake_mode);
-    }
-    // wake items grouped by arithmetic (a template parameter of k_wake)
-    std::vector<Item> witems;
-    for (int mode = kWakeFP32; mode <= kWakeBF16x3; ++mode) {
-        WakeGroup g;
-        g.item0 = (int)witems.size();
-        g.mode = mode;
-        for (int j = 0; j < njobs; ++j)
-            if (jobs[j]->sr_on && jobs[j]->wake_mode == mode) {
-                wake_items(jobs[j], j, witems);
-                g.nbins_max = std::max(g.nbins_max, jobs[j]->nbins());
+        mbt_batch *B = new (std::nothrow) mbt_batch();
+        if (!B)
+            return MBT_ENOMEM;
+        B->jobs.assign(jobs, jobs + njobs);
+        B->work = reinterpret_cast<unsigned char *>(d_work);
+        B->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep, &B->off_wake);
+        // items grouped by long-range count, jobs in the order given
+        std::vector<Item> pitems, citems;
+        Engine &e = B->eng;
+        for (int nlr = 0; nlr <= kMaxLR; ++nlr) {
+            Group g;
+            g.item0 = (int)pitems.size();
+            g.nlr = nlr;
+            g.map = -1;
+            for (int j = 0; j < njobs; ++j) {
+                mbt_ctx *c = jobs[j];
+                if (c->nlr() != nlr)
+                    continue;
+                push_items(c, j, pitems);
+                g.nbins_max = std::max(g.nbins_max, c->nbins());
+                g.nsub_max = std::max(g.nsub_max, c->nsub);
+                const int k = map_kind(c);
+                g.map = (g.map < 0 || g.map == k) ? k : kMapGeneric;
             }
-        g.nitems = (int)witems.size() - g.item0;
-        if (g.nitems > 0)
-            e.wakes.push_back(g);
-    }
-    if (pitems.size() > (size_t)INT32_MAX || citems.size() > (size_t)INT32_MAX) {
-        delete B;
-        return MBT_EINVAL;
-    }
-    e.jobs = reinterpret_cast<const JobDesc *>(B->work);
-    e.push_items = reinterpret_cast<const Item *>(B->work + B->off_push);
-    e.prep_items = reinterpret_cast<const Item *>(B->work + B->off_prep);
-    e.wake_items = reinterpret_cast<const Item *>(B->work + B->off_wake);
-    e.njobs = njobs;
-    e.nprep = (int)citems.size();
-    if (njobs == 1)
-        set_one_job(e, jobs[0]);
-    auto bail = [&](hipError_t r) {
-        std::snprintf(B->err, sizeof B->err, "batch setup failed: %s", hipGetErrorString(r));
-        mbt_batch_destroy(B);
-        return MBT_EDEVICE;
-    };
-    hipError_t r;
-    if ((r = hipHostMalloc((void **)&B->pin_desc, (size_t)njobs * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
-        return bail(r);
-    if ((r = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking)) != hipSuccess)
-        return bail(r);
-    if ((r = hipMemcpyAsync(B->work + B->off_push, pitems.data(), pitems.size() * sizeof(Item),
-                            hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
-        (r = hipMemcpyAsync(B->work + B->off_prep, citems.data(), citems.size() * sizeof(Item),
-                            hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
-        (!witems.empty() &&
-         (r = hipMemcpyAsync(B->work + B->off_wake, witems.data(), witems.size() * sizeof(Item),
-                             hipMemcpyHostToDevice, B->stream)) != hipSuccess) ||
-        (r = hipStreamSynchronize(B->stream)) != hipSuccess)
-        return bail(r);
-    *out = B;
-    return MBT_OK;
+            if (g.map < 0)
+                g.map = kMapGeneric;
+            g.nitems = (int)pitems.size() - g.item0;
+            if (g.nitems > 0)
+                e.groups.push_back(g);
+        }
+        for (int j = 0; j < njobs; ++j) {
+            if (!mfma_wake(jobs[j]))
+                prep_items(jobs[j], j, citems);  // k_wake does a matrix-core job's prep
+            e.nlr_max = std::max(e.nlr_max, jobs[j]->nlr());
+            e.nbins_max = std::max(e.nbins_max, jobs[j]->nbins());
+            B->wake_modes.push_back(jobs[j]->wake_mode);
+        }
+        // wake items grouped by arithmetic (a template parameter of k_wake)
+        std::vector<Item> witems;
+        for (int mode = kWakeFP32; mode <= kWakeBF16x3; ++mode) {
+            WakeGroup g;
+            g.item0 = (int)witems.size();
+            g.mode = mode;
+            for (int j = 0; j < njobs; ++j)
+                if (jobs[j]->sr_on && jobs[j]->wake_mode == mode) {
+                    wake_items(jobs[j], j, witems);
+                    g.nbins_max = std::max(g.nbins_max, jobs[j]->nbins());
+                }
+            g.nitems = (int)witems.size() - g.item0;
+            if (g.nitems > 0)
+                e.wakes.push_back(g);
+        }
+        if (pitems.size() > (size_t)INT32_MAX || citems.size() > (size_t)INT32_MAX) {
+            delete B;
+            return MBT_EINVAL;
+        }
+        e.jobs = reinterpret_cast<const JobDesc *>(B->work);
+        e.push_items = reinterpret_cast<const Item *>(B->work + B->off_push);
+        e.prep_items = reinterpret_cast<const Item *>(B->work + B->off_prep);
+        e.wake_items = reinterpret_cast<const Item *>(B->work + B->off_wake);
+        e.njobs = njobs;
+        e.nprep = (int)citems.size();
+        if (njobs == 1)
+            set_one_job(e, jobs[0]);
+        auto bail = [&](hipError_t r) {
+            std::snprintf(B->err, sizeof B->err, "batch setup failed: %s", hipGetErrorString(r));
+            mbt_batch_destroy(B);
+            return MBT_EDEVICE;
+        };
+        hipError_t r;
+        if ((r = hipHostMalloc((void **)&B->pin_desc, (size_t)njobs * sizeof(JobDesc), hipHostMallocDefault)) != hipSuccess)
+            return bail(r);
+        if ((r = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking)) != hipSuccess)
+            return bail(r);
+        if ((r = hipMemcpyAsync(B->work + B->off_push, pitems.data(), pitems.size() * sizeof(Item),
+                                hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
+            (r = hipMemcpyAsync(B->work + B->off_prep, citems.data(), citems.size() * sizeof(Item),
+                                hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
+            (!witems.empty() &&
+             (r = hipMemcpyAsync(B->work + B->off_wake, witems.data(), witems.size() * sizeof(Item),
+                                 hipMemcpyHostToDevice, B->stream)) != hipSuccess) ||
+            (r = hipStreamSynchronize(B->stream)) != hipSuccess)
+            return bail(r);
+        *out = B;
+        return MBT_OK;
+    });
 }
 
 void mbt_batch_destroy(mbt_batch *B)
 {
-    if (!B)
-        return;
-    (void)hipStreamSynchronize(B->stream);
-    drop_graph(B);
-    if (B->cap)
-        (void)hipStreamDestroy(B->cap);
-    if (B->pin_desc)
-        (void)hipHostFree(B->pin_desc);
-    delete B;
+    try {
+        if (!B)
+            return;
+        (void)hipStreamSynchronize(B->stream);
+        drop_graph(B);
+        if (B->cap)
+            (void)hipStreamDestroy(B->cap);
+        if (B->pin_desc)
+            (void)hipHostFree(B->pin_desc);
+        delete B;
+    } catch (...) {
+        // teardown does not allocate; nothing may leave the ABI
+    }
 }
 
 const char *mbt_batch_last_error(const mbt_batch *B) { return B ? B->err : "null batch"; }
 
 int mbt_batch_configure(mbt_batch *B, int32_t graph_turns, int32_t autotune)
 {
-    if (!B || graph_turns < 0 || graph_turns > 1024 || (autotune != 0 && autotune != 1))
-        return MBT_EINVAL;
-    if (graph_turns != B->graph_turns)
-        drop_graph(B);
-    B->graph_turns = graph_turns;
-    B->autotune = autotune == 1;
-    return MBT_OK;
+    return guarded(B, [&]() -> int {
+        if (!B || graph_turns < 0 || graph_turns > 1024 || (autotune != 0 && autotune != 1))
+            return MBT_EINVAL;
+        if (graph_turns != B->graph_turns)
+            drop_graph(B);
+        B->graph_turns = graph_turns;
+        B->autotune = autotune == 1;
+        return MBT_OK;
+    });
 }
 
 int mbt_batch_launch_info(const mbt_batch *B, int32_t *ngroups, int32_t *nlr, int32_t *nsub,
                           int32_t *grid)
 {
-    if (!B || !ngroups)
-        return MBT_EINVAL;
-    *ngroups = (int32_t)B->eng.groups.size();
-    for (size_t g = 0; g < B->eng.groups.size(); ++g) {
-        const Group &G = B->eng.groups[g];
-        if (nlr)
-            nlr[g] = G.nlr;
-        if (nsub)
-            nsub[g] = G.nsub_max;
-        if (grid)
-            grid[g] = G.grid > 0 ? std::min(G.grid, G.nitems) : G.nitems;
-    }
-    return MBT_OK;
+    return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
+        if (!B || !ngroups)
+            return MBT_EINVAL;
+        *ngroups = (int32_t)B->eng.groups.size();
+        for (size_t g = 0; g < B->eng.groups.size(); ++g) {
+            const Group &G = B->eng.groups[g];
+            if (nlr)
+                nlr[g] = G.nlr;
+            if (nsub)
+                nsub[g] = G.nsub_max;
+            if (grid)
+                grid[g] = G.grid > 0 ? std::min(G.grid, G.nitems) : G.nitems;
+        }
+        return MBT_OK;
+    });
 }
 
 int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
                     uint32_t *const *counts, const int32_t *stride)
 {
-    if (!B)
-        return MBT_EINVAL;
-    const int nj = (int)B->jobs.size();
-    if (nturns < 0 || nturns > INT32_MAX)
-        return fail(B, MBT_EINVAL, "need 0 <= nturns < 2^31");
-    for (int j = 0; j < nj; ++j) {
-        mbt_ctx *c = B->jobs[j];
-        if (!c->bound || !c->have_particles)
-            return fail(B, MBT_ESTATE, "job %d: not bound or particles not initialised", j);
-        if (c->turn + nturns > ((int64_t)1 << 32))
-            return fail(B, MBT_EINVAL, "job %d: turn counter would pass 2^32", j);
-        if (counts && counts[j] && (!c->sr_on || !stride || stride[j] < 1))
-            return fail(B, MBT_EINVAL, "job %d: profiles need a grid and stride >= 1", j);
-        if (c->wake_mode != B->wake_modes[j])
-            return fail(B, MBT_ESTATE, "job %d: wake precision changed after the batch was made", j);
-    }
-    if (nturns == 0)
-        return MBT_OK;
-    // per-job strides (0: no profiles)
-    std::vector<int32_t> st(nj, 0);
-    for (int j = 0; j < nj; ++j)
-        st[j] = (counts && counts[j]) ? stride[j] : 0;
-    // earlier work on the jobs' own streams first
-    for (mbt_ctx *c : B->jobs)
-        if (c->stream_h != B->stream)
-            HIPCHK(B, hipStreamSynchronize(c->stream_h));
-    for (int j = 0; j < nj; ++j) {
-        mbt_ctx *c = B->jobs[j];
-        int rc = begin_call(c, st[j], B->stream);
-        if (rc)
-            return fail(B, rc, "job %d: %s", j, c->err);
-        ring_start(c->mom, out ? out[j] : nullptr);
-        ring_start(c->prof, st[j] ? counts[j] : nullptr);
-    }
-    // LDS bound of each push group from the jobs' present sub-histogram counts
-    for (Group &g : B->eng.groups) {
-        int ns = 0;
+    return guarded(B, [&]() -> int {
+        if (!B)
+            return MBT_EINVAL;
+        const int nj = (int)B->jobs.size();
+        if (nturns < 0 || nturns > INT32_MAX)
+            return fail(B, MBT_EINVAL, "need 0 <= nturns < 2^31");
+        for (int j = 0; j < nj; ++j) {
+            mbt_ctx *c = B->jobs[j];
+            if (!c->bound || !c->have_particles)
+                return fail(B, MBT_ESTATE, "job %d: not bound or particles not initialised", j);
+            if (c->turn + nturns > ((int64_t)1 << 32))
+                return fail(B, MBT_EINVAL, "job %d: turn counter would pass 2^32", j);
+            if (counts && counts[j] && (!c->sr_on || !stride || stride[j] < 1))
+                return fail(B, MBT_EINVAL, "job %d: profiles need a grid and stride >= 1", j);
+            if (c->wake_mode != B->wake_modes[j])
+                return fail(B, MBT_ESTATE, "job %d: wake precision changed after the batch was made", j);
+        }
+        if (nturns == 0)
+            return MBT_OK;
+        // per-job strides (0: no profiles)
+        std::vector<int32_t> st(nj, 0);
+        for (int j = 0; j < nj; ++j)
+            st[j] = (counts && counts[j]) ? stride[j] : 0;
+        // earlier work on the jobs' own streams first
         for (mbt_ctx *c : B->jobs)
-            if (c->nlr() == g.nlr)
-                ns = std::max(ns, c->nsub);
-        if (ns != g.nsub_max)
-            drop_graph(B);
-        g.nsub_max = ns;
-    }
-    int rc = upload_descs(B);
-    if (rc)
-        return rc;
-    int64_t t = 0;
-    if (B->autotune && !B->tuned) {
-        t = batch_tune(B, 0, nturns, st.data(), &rc);
+            if (c->stream_h != B->stream)
+                HIPCHK(B, hipStreamSynchronize(c->stream_h));
+        for (int j = 0; j < nj; ++j) {
+            mbt_ctx *c = B->jobs[j];
+            int rc = begin_call(c, st[j], B->stream);
+            if (rc)
+                return fail(B, rc, "job %d: %s", j, c->err);
+            ring_start(c->mom, out ? out[j] : nullptr);
+            ring_start(c->prof, st[j] ? counts[j] : nullptr);
+        }
+        // LDS bound of each push group from the jobs' present sub-histogram counts
+        for (Group &g : B->eng.groups) {
+            int ns = 0;
+            for (mbt_ctx *c : B->jobs)
+                if (c->nlr() == g.nlr)
+                    ns = std::max(ns, c->nsub);
+            if (ns != g.nsub_max)
+                drop_graph(B);
+            g.nsub_max = ns;
+        }
+        int rc = upload_descs(B);
         if (rc)
             return rc;
-        if (B->tuned)
-            drop_graph(B);
-    }
-    // turns per graph: whole rings' worth of rows at most
-    int G = B->graph_turns;
-    for (int j = 0; j < nj && G > 0; ++j) {
-        mbt_ctx *c = B->jobs[j];
-        G = std::min(G, c->L.mom_slots);
-        if (st[j])
-            G = (int)std::min<int64_t>(G, (int64_t)c->L.prof_slots * st[j]);
-    }
-    G &= ~1;  // an even number of turns leaves the launch phase where it began
-    // capture only when this call replays the graph at least twice (or it is
-    // already captured): a capture costs about as much as a few eager turns
-    const bool have = B->exec_turns == G && B->exec_phase == (int)(t & 1);
-    if (G >= 2 && (have ? t + G <= nturns : t + 2 * G <= nturns)) {
-        if (B->exec_turns != G || B->exec_phase != (int)(t & 1))
-            if ((rc = batch_capture(B, G, (int)(t & 1))))
+        int64_t t = 0;
+        if (B->autotune && !B->tuned) {
+            t = batch_tune(B, 0, nturns, st.data(), &rc);
+            if (rc)
                 return rc;
-        for (; t + G <= nturns; t += G) {
-            if ((rc = batch_rings(B, t, G, st.data())))
+            if (B->tuned)
+                drop_graph(B);
+        }
+        // turns per graph: whole rings' worth of rows at most
+        int G = B->graph_turns;
+        for (int j = 0; j < nj && G > 0; ++j) {
+            mbt_ctx *c = B->jobs[j];
+            G = std::min(G, c->L.mom_slots);
+            if (st[j])
+                G = (int)std::min<int64_t>(G, (int64_t)c->L.prof_slots * st[j]);
+        }
+        G &= ~1;  // an even number of turns leaves the launch phase where it began
+        // capture only when this call replays the graph at least twice (or it is
+        // already captured): a capture costs about as much as a few eager turns
+        const bool have = B->exec_turns == G && B->exec_phase == (int)(t & 1);
+        if (G >= 2 && (have ? t + G <= nturns : t + 2 * G <= nturns)) {
+            if (B->exec_turns != G || B->exec_phase != (int)(t & 1))
+                if ((rc = batch_capture(B, G, (int)(t & 1))))
+                    return rc;
+            for (; t + G <= nturns; t += G) {
+                if ((rc = batch_rings(B, t, G, st.data())))
+                    return rc;
+                HIPCHK(B, hipGraphLaunch(B->exec, B->stream));
+            }
+        }
+        for (; t < nturns; ++t) {
+            if ((rc = batch_rings(B, t, 1, st.data())))
                 return rc;
-            HIPCHK(B, hipGraphLaunch(B->exec, B->stream));
+            HIPCHK(B, enqueue_turn(B->eng, (int)(t & 1), B->stream, nullptr));
         }
-    }
-    for (; t < nturns; ++t) {
-        if ((rc = batch_rings(B, t, 1, st.data())))
-            return rc;
-        HIPCHK(B, enqueue_turn(B->eng, (int)(t & 1), B->stream, nullptr));
-    }
-    for (mbt_ctx *c : B->jobs) {
-        c->turn += nturns;
-        HIPCHK(B, ring_flush(c->mom, B->stream));
-        HIPCHK(B, ring_flush(c->prof, B->stream));
-    }
-    HIPCHK(B, hipStreamSynchronize(B->stream));
-    int bad = -1;
-    for (int j = 0; j < nj; ++j) {
-        mbt_ctx *c = B->jobs[j];
-        HIPCHK(B, ring_land(c->mom));
-        HIPCHK(B, ring_land(c->prof));
-        uint32_t status = 0;
-        HIPCHK(B, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
-        if (status) {
-            HIPCHK(B, hipMemset(c->w<uint32_t>(c->L.status), 0, sizeof status));
-            if (bad < 0)
-                bad = j;
+        for (mbt_ctx *c : B->jobs) {
+            c->turn += nturns;
+            HIPCHK(B, ring_flush(c->mom, B->stream));
+            HIPCHK(B, ring_flush(c->prof, B->stream));
         }
-    }
-    if (bad >= 0)
-        return fail(B, MBT_ENUMERIC, "job %d: non-finite bunch moment", bad);
-    return MBT_OK;
+        HIPCHK(B, hipStreamSynchronize(B->stream));
+        int bad = -1;
+        for (int j = 0; j < nj; ++j) {
+            mbt_ctx *c = B->jobs[j];
+            HIPCHK(B, ring_land(c->mom));
+            HIPCHK(B, ring_land(c->prof));
+            uint32_t status = 0;
+            HIPCHK(B, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
+            if (status) {
+                HIPCHK(B, hipMemset(c->w<uint32_t>(c->L.status), 0, sizeof status));
+                if (bad < 0)
+                    bad = j;
+            }
+        }
+        if (bad >= 0)
+            return fail(B, MBT_ENUMERIC, "job %d: non-finite bunch moment", bad);
+        return MBT_OK;
+    });
 }
 
 }  // extern "C"

@@ -146,3 +146,53 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_abi, "LIB_PATH", "/nonexistent/libmbt.so")
     with pytest.raises(_abi.MissingLibraryError):
         _abi.lib()
+
+
+_ENOMEM_CHILD = r"""
+import ctypes as C, resource, sys
+sys.path.insert(0, sys.argv[1])
+from paper_1809_00391_amd import _abi, tracker as tr
+from paper_1809_00391_amd import workloads as wl
+L = _abi.lib()
+M = 65535
+h = C.c_void_p()
+assert L.mbt_create(C.byref(tr._ring(dict(wl.RING_R480, harmonic=M))), C.byref(h)) == 0
+small = (C.c_int32 * 2)(0, 9)
+cur = (C.c_double * M)(*([1e-3] * M))
+assert L.mbt_set_fill(h, 2, small, cur, None) == 0
+b = (C.c_int32 * M)(*range(M))
+C.CDLL("libc.so.6").malloc_trim(0)
+vm = [int(x.split()[1]) * 1024 for x in open("/proc/self/status") if x.startswith("VmSize:")][0]
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+# no address space beyond what the process holds: the fill's three arrays
+# (about 1 MB) cannot be allocated
+resource.setrlimit(resource.RLIMIT_AS, (vm + 4096, hard))
+rc = L.mbt_set_fill(h, M, b, cur, None)
+resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+msg = L.mbt_last_error(h).decode()
+sb, wb = C.c_size_t(), C.c_size_t()
+q = L.mbt_query_bytes(h, 1000, C.byref(sb), C.byref(wb))
+rc2 = L.mbt_set_fill(h, M, b, cur, None)
+L.mbt_destroy(h)
+print(rc, q, sb.value, rc2, msg)
+"""
+
+
+def test_host_allocation_failure_returns_enomem():
+    """A host allocation that fails inside an entry point comes back as
+    MBT_ENOMEM with a message (no C++ exception leaves the library), and the
+    context keeps its previous, consistent settings.  The failure is forced
+    by capping the child process's address space at what it already holds."""
+    import subprocess
+    import sys
+    root = os.path.dirname(HERE)
+    out = subprocess.run([sys.executable, "-c", _ENOMEM_CHILD, root], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    rc, q, state_bytes, rc2, msg = out.stdout.split(maxsplit=4)
+    assert int(rc) == _abi.MBT_ENOMEM
+    assert "allocation" in msg
+    # the two-bunch fill is still the one in force: 2 bunches x 2 rows x 1024 doubles
+    assert int(q) == 0 and int(state_bytes) == 2 * 2 * 1024 * 8
+    # once memory is there again the same call succeeds
+    assert int(rc2) == 0
