@@ -254,6 +254,90 @@ int mbt_ref_wake_potential(int32_t nbins, const double *W, const uint32_t *count
 }
 
 /* ------------------------------------------------------------------------ */
+/* Transverse wakes (Sec. 2.3, Eq. 6 second line; long-range resistive wall). */
+/* ------------------------------------------------------------------------ */
+
+/* Transverse wake of a resonator (R_s in Ohm/m, Q, omega_r): with
+ * alpha = omega_r / 2Q and wbar = sqrt(omega_r^2 - alpha^2),
+ *   W_T(t) = (R_s omega_r^2 / (Q wbar)) exp(-alpha t) sin(wbar t), t > 0;
+ * it vanishes at t = 0 and before the source passes. */
+double mbt_ref_transverse_resonator_wake(const mbt_ref_resonator *r, double t)
+{
+    if (!(t > 0.0))
+        return 0.0;
+    double wr = TWO_PI * r->fr_Hz;
+    double alpha = wr / (2.0 * r->q);
+    double wbar = sqrt(wr * wr - alpha * alpha);
+    return r->rs_ohm * wr * wr / (r->q * wbar) * exp(-alpha * t) * sin(wbar * t);
+}
+
+/* Thick-wall transverse resistive-wall wake far behind the source: the
+ * impedance Z_T = (2 c / (b^2 w)) Z_L with Z_L = (L / (2 pi b)) (1 + i)
+ * sqrt(w mu0 / (2 sigma)) transforms to (L / (pi b^3)) sqrt(Z0 c / (pi sigma t)). */
+double mbt_ref_transverse_rw_wake(const mbt_ref_rw *rw, double t)
+{
+    if (!(t > 0.0))
+        return 0.0;
+    const double c = 299792458.0, z0 = 376.730313668;
+    const double b = rw->radius_m;
+    return rw->length_m / (PI * b * b * b) * sqrt(z0 * c / (PI * rw->conductivity_S_m * t));
+}
+
+int mbt_ref_transverse_wake_table(int32_t nres, const mbt_ref_resonator *res,
+                                  const mbt_ref_grid *g, double *T)
+{
+    if (!grid_ok(g) || nres < 0 || (nres > 0 && !res) || !T)
+        return MBT_REF_EINVAL;
+    double delta_t = (g->tau_max_s - g->tau_min_s) / (double)g->nbins;
+    for (int32_t k = 0; k < g->nbins; ++k)
+        T[k] = 0.0;
+    for (int32_t i = 0; i < nres; ++i) {
+        if (!res_ok(&res[i]))
+            return MBT_REF_EINVAL;
+        for (int32_t k = 1; k < g->nbins; ++k)
+            T[k] += mbt_ref_transverse_resonator_wake(&res[i], (double)k * delta_t);
+    }
+    return MBT_REF_OK;
+}
+
+/* Sec. 2.3: count the particles of every bin and sum their x (the dipole
+ * moment of the bin times its count). */
+int mbt_ref_dipole_histogram(const mbt_ref_grid *g, int64_t n, const double *tau,
+                             const double *x, uint32_t *counts, double *X)
+{
+    if (!grid_ok(g) || n < 0 || (n > 0 && (!tau || !x)) || !counts || !X)
+        return MBT_REF_EINVAL;
+    for (int32_t k = 0; k < g->nbins; ++k) {
+        counts[k] = 0;
+        X[k] = 0.0;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t k = mbt_ref_bin_index(g, tau[j]);
+        if (k >= 0) {
+            ++counts[k];
+            X[k] += x[j];
+        }
+    }
+    return MBT_REF_OK;
+}
+
+/* Eq. 6, second line: the kick on bin k comes from the dipoles of the bins
+ * that passed before it, U[k] = scale * sum_{m<k} T[k-m] X[m]. */
+int mbt_ref_transverse_kicks(int32_t nbins, const double *T, const double *X, double scale,
+                             double *U)
+{
+    if (nbins < 1 || !T || !X || !U)
+        return MBT_REF_EINVAL;
+    for (int32_t k = 0; k < nbins; ++k) {
+        double acc = 0.0;
+        for (int32_t m = 0; m < k; ++m)
+            acc += T[k - m] * X[m];
+        U[k] = scale * acc;
+    }
+    return MBT_REF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Harmonic cavity.                                                          */
 /* ------------------------------------------------------------------------ */
 
@@ -318,9 +402,20 @@ struct mbt_ref_sim {
     double complex lr_c[MAX_RES];
     double complex phasor[MAX_RES];
     double complex *gap; /* [n_lr][M] rotation into bunch b's bucket */
+    /* transverse plane */
+    int tr_on;
+    mbt_ref_transverse tr;
+    double tr_qfrac, tr_gamma, tr_noise_x, tr_noise_xp;
+    int32_t n_tw;
+    mbt_ref_resonator tw[MAX_RES];
+    double *T; /* transverse wake table, rebuilt by prepare() */
+    int lrrw_on;
+    mbt_ref_lrrw lrrw;
+    double *H; /* [turns][M] centroid history of the long-range wall */
     /* particles */
     int64_t N;
     double *tau, *delta;
+    double *x, *xp; /* transverse coordinates (with the plane on) */
     uint64_t seed;
     int64_t turn;
     int prepared;
@@ -422,6 +517,10 @@ void mbt_ref_destroy(mbt_ref_sim *s)
     free(s->gap);
     free(s->tau);
     free(s->delta);
+    free(s->x);
+    free(s->xp);
+    free(s->T);
+    free(s->H);
     free(s);
 }
 
@@ -489,6 +588,8 @@ int mbt_ref_set_fill(mbt_ref_sim *s, int32_t M, const int32_t *bucket, const dou
         s->stream[b] = stream ? stream[b] : b;
     }
     s->M = M;
+    free(s->H);
+    s->H = NULL;
     s->prepared = 0;
     return MBT_REF_OK;
 }
@@ -580,6 +681,21 @@ static int prepare(mbt_ref_sim *s)
         if (rc)
             return fail(s, rc, "wake table");
     }
+    free(s->T);
+    s->T = NULL;
+    if (s->sr_on && s->tr_on) {
+        s->T = malloc(sizeof(double) * (size_t)s->grid.nbins);
+        if (!s->T)
+            return fail(s, MBT_REF_ENOMEM, "out of memory");
+        int rc = mbt_ref_transverse_wake_table(s->n_tw, s->tw, &s->grid, s->T);
+        if (rc)
+            return fail(s, rc, "transverse wake table");
+    }
+    if (s->tr_on && s->lrrw_on && !s->H) {
+        s->H = calloc((size_t)s->lrrw.turns * (size_t)s->M, sizeof(double));
+        if (!s->H)
+            return fail(s, MBT_REF_ENOMEM, "out of memory");
+    }
     free(s->gap);
     s->gap = NULL;
     if (s->n_lr > 0) {
@@ -622,11 +738,22 @@ int mbt_ref_alloc_particles(mbt_ref_sim *s, int64_t N, uint64_t seed)
         s->tau = s->delta = NULL;
         return fail(s, MBT_REF_ENOMEM, "out of memory for %zu particles", n);
     }
+    free(s->x);
+    free(s->xp);
+    s->x = s->xp = NULL;
+    if (s->tr_on) {
+        s->x = calloc(n, sizeof(double));
+        s->xp = calloc(n, sizeof(double));
+        if (!s->x || !s->xp)
+            return fail(s, MBT_REF_ENOMEM, "out of memory for %zu transverse particles", n);
+    }
     s->N = N;
     s->seed = seed;
     s->turn = 0;
     for (int32_t r = 0; r < MAX_RES; ++r)
         s->phasor[r] = 0.0;
+    if (s->H)
+        memset(s->H, 0, sizeof(double) * (size_t)s->lrrw.turns * (size_t)s->M);
     return MBT_REF_OK;
 }
 
@@ -676,6 +803,157 @@ int mbt_ref_get_particles(const mbt_ref_sim *s, int32_t bunch, double *tau, doub
         return MBT_REF_EINVAL;
     memcpy(tau, s->tau + (size_t)bunch * (size_t)s->N, sizeof(double) * (size_t)s->N);
     memcpy(delta, s->delta + (size_t)bunch * (size_t)s->N, sizeof(double) * (size_t)s->N);
+    return MBT_REF_OK;
+}
+
+int mbt_ref_set_transverse(mbt_ref_sim *s, const mbt_ref_transverse *tr)
+{
+    if (!s)
+        return MBT_REF_EINVAL;
+    if (!tr) {
+        s->tr_on = 0;
+        free(s->x);
+        free(s->xp);
+        s->x = s->xp = NULL;
+        s->prepared = 0;
+        return MBT_REF_OK;
+    }
+    if (!isfinite(tr->tune) || !isfinite(tr->chromaticity) || !isfinite(tr->alpha) ||
+        !(tr->beta_m > 0.0) || !isfinite(tr->beta_m) || !isfinite(tr->disp_m) ||
+        !isfinite(tr->disp_prime) || !(tr->emittance_m >= 0.0) || !isfinite(tr->emittance_m) ||
+        !(tr->tau_damp_s > 0.0))
+        return fail(s, MBT_REF_EINVAL, "bad transverse plane");
+    s->tr = *tr;
+    /* the one-turn matrix depends on the phase modulo 2 pi: the integer part
+     * of the tune is dropped, exactly (Sterbenz) */
+    s->tr_qfrac = tr->tune - floor(tr->tune);
+    s->tr_gamma = (1.0 + tr->alpha * tr->alpha) / tr->beta_m;
+    /* Eq. 5: noise sigma sqrt(D_x) with D_x = 2 T0 / tau (as for delta) */
+    double dx = 2.0 * s->T0 / tr->tau_damp_s;
+    s->tr_noise_x = sqrt(tr->emittance_m * tr->beta_m) * sqrt(dx);
+    s->tr_noise_xp = sqrt(tr->emittance_m * s->tr_gamma) * sqrt(dx);
+    if (!s->tr_on && s->tau) {
+        size_t n = (size_t)s->M * (size_t)s->N;
+        s->x = calloc(n, sizeof(double));
+        s->xp = calloc(n, sizeof(double));
+        if (!s->x || !s->xp) {
+            free(s->x);
+            free(s->xp);
+            s->x = s->xp = NULL;
+            return fail(s, MBT_REF_ENOMEM, "out of memory");
+        }
+    }
+    s->tr_on = 1;
+    s->prepared = 0;
+    return MBT_REF_OK;
+}
+
+int mbt_ref_set_transverse_wake(mbt_ref_sim *s, int32_t nres, const mbt_ref_resonator *res)
+{
+    if (!s)
+        return MBT_REF_EINVAL;
+    if (nres < 0 || nres > MAX_RES || (nres > 0 && !res))
+        return fail(s, MBT_REF_EINVAL, "bad transverse resonator list");
+    for (int32_t i = 0; i < nres; ++i)
+        if (!res_ok(&res[i]))
+            return fail(s, MBT_REF_EINVAL, "resonator %d: need Rs >= 0, Q > 0.5, fr > 0", i);
+    s->n_tw = nres;
+    for (int32_t i = 0; i < nres; ++i)
+        s->tw[i] = res[i];
+    s->prepared = 0;
+    return MBT_REF_OK;
+}
+
+int mbt_ref_set_transverse_rw(mbt_ref_sim *s, const mbt_ref_lrrw *rw)
+{
+    if (!s)
+        return MBT_REF_EINVAL;
+    if (rw) {
+        mbt_ref_rw w = {rw->radius_m, rw->conductivity_S_m, rw->length_m};
+        if (!rw_ok(&w) || rw->turns < 1 || rw->turns > 1024)
+            return fail(s, MBT_REF_EINVAL, "resistive wall: need radius, conductivity, length > 0 "
+                                           "and 1 <= turns <= 1024");
+        s->lrrw = *rw;
+    }
+    s->lrrw_on = rw != NULL;
+    free(s->H);
+    s->H = NULL;
+    s->prepared = 0;
+    return MBT_REF_OK;
+}
+
+/* Matched Gaussian betatron coordinates from the INIT stream, tag 4: one
+ * Box-Muller pair per particle, z0 for x and z1 for x'. */
+int mbt_ref_init_transverse(mbt_ref_sim *s, double emittance_m, double offset_m)
+{
+    if (!s)
+        return MBT_REF_EINVAL;
+    if (!s->tr_on || !s->x)
+        return fail(s, MBT_REF_ESTATE, "transverse plane or particles not set");
+    if (!(emittance_m >= 0.0) || !isfinite(emittance_m) || !isfinite(offset_m))
+        return fail(s, MBT_REF_EINVAL, "emittance must be finite and >= 0");
+    const double sx = sqrt(emittance_m * s->tr.beta_m), sxp = sqrt(emittance_m / s->tr.beta_m);
+    for (int32_t b = 0; b < s->M; ++b) {
+        double *x = s->x + (size_t)b * (size_t)s->N;
+        double *xp = s->xp + (size_t)b * (size_t)s->N;
+        for (int64_t j = 0; j < s->N; ++j) {
+            uint32_t c[4] = {(uint32_t)j, (uint32_t)s->stream[b], 0u, 4u};
+            double z[2];
+            mbt_ref_normal_pair(s->seed, c, z);
+            x[j] = offset_m + sx * z[0];
+            xp[j] = sxp * (z[1] - s->tr.alpha * z[0]);
+        }
+    }
+    if (s->H)
+        memset(s->H, 0, sizeof(double) * (size_t)s->lrrw.turns * (size_t)s->M);
+    return MBT_REF_OK;
+}
+
+int mbt_ref_set_transverse_particles(mbt_ref_sim *s, int32_t bunch, const double *x,
+                                     const double *xp)
+{
+    if (!s)
+        return MBT_REF_EINVAL;
+    if (!s->x)
+        return fail(s, MBT_REF_ESTATE, "transverse particles not allocated");
+    if (bunch < 0 || bunch >= s->M || !x || !xp)
+        return fail(s, MBT_REF_EINVAL, "bad bunch index or null array");
+    memcpy(s->x + (size_t)bunch * (size_t)s->N, x, sizeof(double) * (size_t)s->N);
+    memcpy(s->xp + (size_t)bunch * (size_t)s->N, xp, sizeof(double) * (size_t)s->N);
+    return MBT_REF_OK;
+}
+
+int mbt_ref_get_transverse_particles(const mbt_ref_sim *s, int32_t bunch, double *x, double *xp)
+{
+    if (!s || !s->x || bunch < 0 || bunch >= s->M || !x || !xp)
+        return MBT_REF_EINVAL;
+    memcpy(x, s->x + (size_t)bunch * (size_t)s->N, sizeof(double) * (size_t)s->N);
+    memcpy(xp, s->xp + (size_t)bunch * (size_t)s->N, sizeof(double) * (size_t)s->N);
+    return MBT_REF_OK;
+}
+
+int mbt_ref_get_rw_history(const mbt_ref_sim *s, double *H)
+{
+    if (!s || !H || !s->lrrw_on || s->M < 1)
+        return MBT_REF_EINVAL;
+    size_t n = (size_t)s->lrrw.turns * (size_t)s->M;
+    if (s->H)
+        memcpy(H, s->H, sizeof(double) * n);
+    else
+        memset(H, 0, sizeof(double) * n);
+    return MBT_REF_OK;
+}
+
+int mbt_ref_set_rw_history(mbt_ref_sim *s, const double *H)
+{
+    if (!s || !H)
+        return MBT_REF_EINVAL;
+    if (!s->lrrw_on || !s->tr_on || s->M < 1)
+        return fail(s, MBT_REF_ESTATE, "no long-range resistive wall");
+    int rc = prepare(s);
+    if (rc)
+        return rc;
+    memcpy(s->H, H, sizeof(double) * (size_t)s->lrrw.turns * (size_t)s->M);
     return MBT_REF_OK;
 }
 
@@ -751,18 +1029,28 @@ static void bunch_moments(int64_t N, const double *tau, const double *del, doubl
 /* One turn of one bunch: binning, wake potential, long-range voltage seen,
  * then the single-particle map for every particle, then the bunch's deposit
  * into the long-range phasors. */
-static int track_bunch(mbt_ref_sim *s, int32_t b, uint32_t *counts, double *V, double *dep)
+static int track_bunch(mbt_ref_sim *s, int32_t b, uint32_t *counts, double *V, double *dep,
+                       double *X, double *U)
 {
     const int64_t N = s->N;
     double *tau = s->tau + (size_t)b * (size_t)N;
     double *del = s->delta + (size_t)b * (size_t)N;
+    const int tr_on = s->tr_on;
+    double *xs = tr_on ? s->x + (size_t)b * (size_t)N : NULL;
+    double *xps = tr_on ? s->xp + (size_t)b * (size_t)N : NULL;
     /* Charge carried by one macro-particle: bunch charge I_b T0 over N. */
     const double q_pp = s->current[b] * s->T0 / (double)N;
 
-    /* Sec. 2.3: assign particles to bins, count them, build the wake
-     * potential of the bunch at every bin. */
+    /* Sec. 2.3: assign particles to bins, count them (and sum their x: the
+     * bins' dipole moments), build the wake potential of the bunch at every
+     * bin and, with the transverse plane, every bin's transverse kick. */
     if (s->sr_on) {
-        mbt_ref_histogram(&s->grid, N, tau, counts, NULL);
+        if (tr_on) {
+            mbt_ref_dipole_histogram(&s->grid, N, tau, xs, counts, X);
+            mbt_ref_transverse_kicks(s->grid.nbins, s->T, X, q_pp / s->ring.energy_eV, U);
+        } else {
+            mbt_ref_histogram(&s->grid, N, tau, counts, NULL);
+        }
         mbt_ref_wake_potential(s->grid.nbins, s->W, counts, q_pp, V);
     }
 
@@ -796,18 +1084,49 @@ static int track_bunch(mbt_ref_sim *s, int32_t b, uint32_t *counts, double *V, d
 #pragma omp parallel for schedule(static) if (N >= 4096)
     for (int64_t j = 0; j < N; ++j) {
         double t = tau[j];
+        const double d_in = del[j];
         /* Eq. 1: energy gain in the RF (main cavity plus harmonic cavity)
          * minus the energy radiated per turn. */
-        double dE = Vrf * sin(phi_s - w * t);
+        double e_rf = Vrf * sin(phi_s - w * t);
         if (hc_on)
-            dE += k_hc * Vrf * sin(nphi - n_hc * w * t);
-        dE -= U0;
+            e_rf += k_hc * Vrf * sin(nphi - n_hc * w * t);
+        double dE = e_rf - U0;
         /* Eq. 6: every particle in bin k loses the bunch's wake voltage V[k];
          * particles outside the grid get no short-range kick. */
+        int32_t k = -1;
         if (sr_on) {
-            int32_t k = mbt_ref_bin_index(&s->grid, t);
+            k = mbt_ref_bin_index(&s->grid, t);
             if (k >= 0)
                 dE -= V[k];
+        }
+        if (tr_on) {
+            /* Eq. 6, second line: the bin's transverse wake kick. */
+            double xp = xps[j];
+            if (k >= 0)
+                xp += U[k];
+            /* Eqs. 3-4: betatron rotation about the dispersive orbit
+             * (D delta, D' delta) by the chromatic phase advance. */
+            const double psi = TWO_PI * (s->tr_qfrac + s->tr.chromaticity * d_in);
+            const double cs = cos(psi), sn = sin(psi);
+            const double al = s->tr.alpha, be = s->tr.beta_m, ga = s->tr_gamma;
+            const double xb = xs[j] - s->tr.disp_m * d_in;
+            const double xpb = xp - s->tr.disp_prime * d_in;
+            double x2 = s->tr.disp_m * d_in + (cs + al * sn) * xb + be * sn * xpb;
+            double xp2 = s->tr.disp_prime * d_in - ga * sn * xb + (cs - al * sn) * xpb;
+            /* Eq. 5: x' shrinks by the momentum ratio across the RF energy
+             * gain (adiabatic damping), then both get their noise. */
+            xp2 = xp2 * ((1.0 + d_in) / (1.0 + d_in + e_rf / E0));
+            if (s->tr_noise_x > 0.0 || s->tr_noise_xp > 0.0) {
+                uint32_t cx[4] = {(uint32_t)(j >> 1), stream, turn, 2u};
+                uint32_t cxp[4] = {(uint32_t)(j >> 1), stream, turn, 3u};
+                double zx[2], zxp[2];
+                mbt_ref_normal_pair(seed, cx, zx);
+                mbt_ref_normal_pair(seed, cxp, zxp);
+                x2 += s->tr_noise_x * zx[j & 1];
+                xp2 += s->tr_noise_xp * zxp[j & 1];
+            }
+            xs[j] = x2;
+            xps[j] = xp2;
         }
         /* Long-range: voltage Re[V~ exp((-alpha + i wbar) tau)]. */
         for (int32_t r = 0; r < n_lr; ++r) {
@@ -815,7 +1134,7 @@ static int track_bunch(mbt_ref_sim *s, int32_t b, uint32_t *counts, double *V, d
             double c = cos(s->lr_wbar[r] * t), sn = sin(s->lr_wbar[r] * t);
             dE -= e * (creal(seen[r]) * c - cimag(seen[r]) * sn);
         }
-        double d = del[j] + dE / E0;
+        double d = d_in + dE / E0;
         /* Eq. 5: radiation damping and quantum excitation. */
         d = d * (1.0 - D);
         if (noise > 0.0) {
@@ -843,11 +1162,49 @@ static int track_bunch(mbt_ref_sim *s, int32_t b, uint32_t *counts, double *V, d
     return MBT_REF_OK;
 }
 
+/* Sec. 2.3, last paragraph: once every bunch has passed and its statistics
+ * are updated, each bunch b gets the long-range resistive-wall kick of the
+ * passages before its own in that turn: bunches b' < b of the same turn and
+ * every bunch of the earlier turns kept in the history, each source a rigid
+ * dipole of charge I_b' T0 at its centroid.  `target` is the turn whose
+ * passages receive the kick; H holds the centroids of turns target-K+1 ..
+ * target.  kick[b] is added to x' of every particle of bunch b. */
+static void rw_kicks(const mbt_ref_sim *s, int64_t target, double *kick)
+{
+    const int32_t K = s->lrrw.turns, M = s->M;
+    const mbt_ref_rw w = {s->lrrw.radius_m, s->lrrw.conductivity_S_m, s->lrrw.length_m};
+    for (int32_t b = 0; b < M; ++b) {
+        double acc = 0.0;
+        for (int32_t age = K - 1; age >= 0; --age) { /* oldest source turn first */
+            const int64_t m = target - age;
+            if (m < 0)
+                continue;
+            const double *row = s->H + (size_t)(m % K) * (size_t)M;
+            for (int32_t bs = 0; bs < M; ++bs) {
+                if (age == 0 && bs >= b)
+                    break;
+                const double dt = (double)age * s->T0 +
+                                  (double)(s->bucket[b] - s->bucket[bs]) * s->T_rf;
+                acc += s->current[bs] * s->T0 * row[bs] * mbt_ref_transverse_rw_wake(&w, dt);
+            }
+        }
+        kick[b] = acc / s->ring.energy_eV;
+    }
+}
+
 int mbt_ref_track(mbt_ref_sim *s, int64_t nturns, double *moments, uint32_t *counts,
                   int32_t stride)
 {
+    return mbt_ref_track2(s, nturns, moments, NULL, counts, stride);
+}
+
+int mbt_ref_track2(mbt_ref_sim *s, int64_t nturns, double *moments, double *tmoments,
+                   uint32_t *counts, int32_t stride)
+{
     if (!s)
         return MBT_REF_EINVAL;
+    if (tmoments && !s->tr_on)
+        return fail(s, MBT_REF_EINVAL, "transverse moments need the transverse plane");
     if (!s->tau)
         return fail(s, MBT_REF_ESTATE, "particles not initialised");
     if (nturns < 0 || s->turn + nturns > (int64_t)UINT32_MAX + 1)
@@ -858,30 +1215,59 @@ int mbt_ref_track(mbt_ref_sim *s, int64_t nturns, double *moments, uint32_t *cou
     if (rc)
         return rc;
     const int32_t nb = s->sr_on ? s->grid.nbins : 1;
+    const int rw = s->tr_on && s->lrrw_on;
     uint32_t *cnt = malloc(sizeof(uint32_t) * (size_t)nb);
     double *V = malloc(sizeof(double) * (size_t)nb);
+    double *X = malloc(sizeof(double) * (size_t)nb);
+    double *U = malloc(sizeof(double) * (size_t)nb);
+    double *kick = malloc(sizeof(double) * (size_t)s->M);
     double *dep = s->n_lr ? malloc(sizeof(double) * 2 * (size_t)s->n_lr * (size_t)s->N) : NULL;
-    if (!cnt || !V || (s->n_lr && !dep)) {
+    if (!cnt || !V || !X || !U || !kick || (s->n_lr && !dep)) {
         free(cnt);
         free(V);
+        free(X);
+        free(U);
+        free(kick);
         free(dep);
         return fail(s, MBT_REF_ENOMEM, "out of memory");
     }
-    for (int64_t t = 0; t < nturns; ++t) {
+    rc = MBT_REF_OK;
+    for (int64_t t = 0; t < nturns && !rc; ++t) {
+        if (rw) {
+            /* the wall's kick of the previous turn's passages, given after
+             * all bunches of that turn (applied here, before this turn) */
+            rw_kicks(s, s->turn - 1, kick);
+            for (int32_t b = 0; b < s->M; ++b)
+                for (int64_t j = 0; j < s->N; ++j)
+                    s->xp[(size_t)b * s->N + j] += kick[b];
+        }
         for (int32_t b = 0; b < s->M; ++b) {
-            track_bunch(s, b, cnt, V, dep);
+            track_bunch(s, b, cnt, V, dep, X, U);
             double m[4];
             bunch_moments(s->N, s->tau + (size_t)b * s->N, s->delta + (size_t)b * s->N, m);
             if (!isfinite(m[0]) || !isfinite(m[1]) || !isfinite(m[2]) || !isfinite(m[3])) {
-                free(cnt);
-                free(V);
-                free(dep);
-                return fail(s, MBT_REF_ENUMERIC, "non-finite moment at turn %lld bunch %d",
-                            (long long)s->turn, b);
+                rc = fail(s, MBT_REF_ENUMERIC, "non-finite moment at turn %lld bunch %d",
+                          (long long)s->turn, b);
+                break;
             }
             if (moments)
                 memcpy(moments + ((size_t)t * s->M + b) * 4, m, sizeof m);
+            if (s->tr_on) {
+                double mx[4];
+                bunch_moments(s->N, s->x + (size_t)b * s->N, s->xp + (size_t)b * s->N, mx);
+                if (!isfinite(mx[0]) || !isfinite(mx[1]) || !isfinite(mx[2]) || !isfinite(mx[3])) {
+                    rc = fail(s, MBT_REF_ENUMERIC, "non-finite transverse moment at turn %lld "
+                              "bunch %d", (long long)s->turn, b);
+                    break;
+                }
+                if (tmoments)
+                    memcpy(tmoments + ((size_t)t * s->M + b) * 4, mx, sizeof mx);
+                if (rw)
+                    s->H[(size_t)(s->turn % s->lrrw.turns) * s->M + b] = mx[0];
+            }
         }
+        if (rc)
+            break;
         if (counts && t % stride == 0) {
             size_t row = (size_t)(t / stride);
             for (int32_t b = 0; b < s->M; ++b)
@@ -892,6 +1278,9 @@ int mbt_ref_track(mbt_ref_sim *s, int64_t nturns, double *moments, uint32_t *cou
     }
     free(cnt);
     free(V);
+    free(X);
+    free(U);
+    free(kick);
     free(dep);
-    return MBT_REF_OK;
+    return rc;
 }

@@ -74,6 +74,31 @@ typedef struct {
     double length_m;
 } mbt_ref_rw;
 
+/* One transverse plane, (x, x') (Sec. 2.2 Eqs. 3-5; the horizontal plane
+ * with its dispersion, or the vertical one with D = D' = 0). */
+typedef struct {
+    double tune;          /* betatron tune Q per turn; only frac(Q) enters the matrix  */
+    double chromaticity;  /* Q' = dQ/ddelta: phase advance 2 pi (frac(Q) + Q' delta)    */
+    double alpha;         /* Twiss alpha at the observation point                       */
+    double beta_m;        /* Twiss beta [m], > 0; gamma = (1 + alpha^2) / beta           */
+    double disp_m;        /* dispersion D [m]                                           */
+    double disp_prime;    /* dispersion slope D'                                        */
+    double emittance_m;   /* equilibrium emittance eps: the noise scales are
+                             sigma_x = sqrt(eps beta), sigma_x' = sqrt(eps gamma)       */
+    double tau_damp_s;    /* amplitude damping time of the plane, D_x = 2 T0 / tau;
+                             +inf (or eps = 0) switches the plane's noise off          */
+} mbt_ref_transverse;
+
+/* Long-range transverse resistive wall (Sec. 2.3, last paragraph): a round
+ * pipe of the given radius, DC conductivity and length, acting from every
+ * earlier bunch passage of the last `turns` turns (the present one included). */
+typedef struct {
+    double radius_m;
+    double conductivity_S_m;
+    double length_m;
+    int32_t turns;        /* 1 .. 1024 */
+} mbt_ref_lrrw;
+
 typedef struct mbt_ref_sim mbt_ref_sim;
 
 /* ---- free functions (also used as pins) ---------------------------------- */
@@ -116,6 +141,32 @@ int mbt_ref_histogram(const mbt_ref_grid *g, int64_t n, const double *tau,
 int mbt_ref_wake_potential(int32_t nbins, const double *W, const uint32_t *counts,
                            double q_per_particle, double *V);
 
+/* Transverse wake of a resonator with R_s in Ohm/m: for t > 0
+ *   W_T(t) = (R_s omega_r^2 / (Q wbar)) exp(-alpha t) sin(wbar t)  [V/(C m)],
+ * 0 for t <= 0. */
+double mbt_ref_transverse_resonator_wake(const mbt_ref_resonator *r, double t);
+
+/* Long-range transverse wake of a thick resistive round pipe (the 1/sqrt(t)
+ * law of the low-frequency impedance), for t > 0:
+ *   W_T(t) = (L / (pi b^3)) sqrt(Z0 c / (pi sigma t))  [V/(C m)]; 0 for t <= 0. */
+double mbt_ref_transverse_rw_wake(const mbt_ref_rw *rw, double t);
+
+/* Transverse wake table: T[0] = 0, T[k] = sum over resonators of W_T(k Delta). */
+int mbt_ref_transverse_wake_table(int32_t nres, const mbt_ref_resonator *res,
+                                  const mbt_ref_grid *g, double *T);
+
+/* Counts and dipole sums of n particles: X[k] = sum of x over the particles
+ * in bin k, added in particle order (the bin's dipole moment times its
+ * count). */
+int mbt_ref_dipole_histogram(const mbt_ref_grid *g, int64_t n, const double *tau,
+                             const double *x, uint32_t *counts, double *X);
+
+/* Transverse kick of bin k from the dipole sums of the bins before it
+ * (Eq. 6, second line): U[k] = scale * sum_{m<k} T[k-m] X[m], m ascending;
+ * scale = q_per_particle / E0. */
+int mbt_ref_transverse_kicks(int32_t nbins, const double *T, const double *X, double scale,
+                             double *U);
+
 /* Harmonic cavity at a fraction of the flat-potential voltage. */
 int mbt_ref_hc_flat_fraction(const mbt_ref_ring *ring, int32_t n, double frac,
                              mbt_ref_hc *out);
@@ -153,6 +204,32 @@ int mbt_ref_get_particles(const mbt_ref_sim *s, int32_t bunch, double *tau,
  * 0, stride, 2*stride, ... of this call (may be NULL). */
 int mbt_ref_track(mbt_ref_sim *s, int64_t nturns, double *moments,
                   uint32_t *counts, int32_t stride);
+
+/* Transverse plane (NULL switches it off).  Must precede the particles.
+ * MBT_REF_EINVAL on beta <= 0, eps < 0, tau <= 0 or a non-finite value. */
+int mbt_ref_set_transverse(mbt_ref_sim *s, const mbt_ref_transverse *tr);
+/* Transverse short-range resonators (R_s in Ohm/m), on the short-range grid. */
+int mbt_ref_set_transverse_wake(mbt_ref_sim *s, int32_t nres, const mbt_ref_resonator *res);
+/* Long-range transverse resistive wall (NULL: off). */
+int mbt_ref_set_transverse_rw(mbt_ref_sim *s, const mbt_ref_lrrw *rw);
+/* Matched Gaussian (x, x') for every particle from the INIT stream (tag 4):
+ * x = offset + sqrt(eps beta) z0, x' = sqrt(eps / beta) (z1 - alpha z0);
+ * clears the resistive-wall history.  Needs the transverse plane and the
+ * particles allocated. */
+int mbt_ref_init_transverse(mbt_ref_sim *s, double emittance_m, double offset_m);
+int mbt_ref_set_transverse_particles(mbt_ref_sim *s, int32_t bunch, const double *x,
+                                     const double *xp);
+int mbt_ref_get_transverse_particles(const mbt_ref_sim *s, int32_t bunch, double *x,
+                                     double *xp);
+/* As mbt_ref_track, plus tmoments [nturns][M][4] = mean x, mean x', rms x,
+ * rms x' of the state after each turn (may be NULL; needs the plane). */
+int mbt_ref_track2(mbt_ref_sim *s, int64_t nturns, double *moments, double *tmoments,
+                   uint32_t *counts, int32_t stride);
+/* Resistive-wall history: bunch centroids <x> of the last `turns` turns,
+ * [turns][M], row r holding the turn t with t mod turns == r (zeros for
+ * turns before 0).  Part of a checkpoint, beside mbt_ref_get_state. */
+int mbt_ref_get_rw_history(const mbt_ref_sim *s, double *H);
+int mbt_ref_set_rw_history(mbt_ref_sim *s, const double *H);
 
 /* Checkpoint: turn counter, seed and long-range phasors ([nlr][2] re, im). */
 int mbt_ref_get_state(const mbt_ref_sim *s, int64_t *turn, uint64_t *seed, double *phasors);

@@ -37,6 +37,17 @@ class RefRW(C.Structure):
                 ("length_m", C.c_double)]
 
 
+class RefTransverse(C.Structure):
+    _fields_ = [("tune", C.c_double), ("chromaticity", C.c_double), ("alpha", C.c_double),
+                ("beta_m", C.c_double), ("disp_m", C.c_double), ("disp_prime", C.c_double),
+                ("emittance_m", C.c_double), ("tau_damp_s", C.c_double)]
+
+
+class RefLRRW(C.Structure):
+    _fields_ = [("radius_m", C.c_double), ("conductivity_S_m", C.c_double),
+                ("length_m", C.c_double), ("turns", C.c_int32)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -74,6 +85,20 @@ def lib():
             "mbt_ref_derived": (C.c_int, [sims, dp]),
             "mbt_ref_threads": (C.c_int, []),
             "mbt_ref_set_threads": (C.c_int, [C.c_int]),
+            "mbt_ref_transverse_resonator_wake": (C.c_double, [P(RefResonator), C.c_double]),
+            "mbt_ref_transverse_rw_wake": (C.c_double, [P(RefRW), C.c_double]),
+            "mbt_ref_transverse_wake_table": (C.c_int, [C.c_int32, P(RefResonator), P(RefGrid), dp]),
+            "mbt_ref_dipole_histogram": (C.c_int, [P(RefGrid), C.c_int64, dp, dp, up, dp]),
+            "mbt_ref_transverse_kicks": (C.c_int, [C.c_int32, dp, dp, C.c_double, dp]),
+            "mbt_ref_set_transverse": (C.c_int, [sims, P(RefTransverse)]),
+            "mbt_ref_set_transverse_wake": (C.c_int, [sims, C.c_int32, P(RefResonator)]),
+            "mbt_ref_set_transverse_rw": (C.c_int, [sims, P(RefLRRW)]),
+            "mbt_ref_init_transverse": (C.c_int, [sims, C.c_double, C.c_double]),
+            "mbt_ref_set_transverse_particles": (C.c_int, [sims, C.c_int32, dp, dp]),
+            "mbt_ref_get_transverse_particles": (C.c_int, [sims, C.c_int32, dp, dp]),
+            "mbt_ref_track2": (C.c_int, [sims, C.c_int64, dp, dp, up, C.c_int32]),
+            "mbt_ref_get_rw_history": (C.c_int, [sims, dp]),
+            "mbt_ref_set_rw_history": (C.c_int, [sims, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -172,6 +197,48 @@ def hc_flat_fraction(ring, n, frac):
     if rc:
         raise OracleError(rc, "hc_flat_fraction")
     return {"n": out.n, "v_ratio": out.v_ratio, "phase_n_rad": out.phase_n_rad}
+
+
+def transverse_resonator_wake(rs, q, fr, t):
+    """Transverse resonator wake in V/(C m) (R_s in Ohm/m)."""
+    return lib().mbt_ref_transverse_resonator_wake(C.byref(RefResonator(rs, q, fr)), float(t))
+
+
+def transverse_rw_wake(rw, t):
+    """Long-range transverse resistive-wall wake; rw = (radius, conductivity, length)."""
+    return lib().mbt_ref_transverse_rw_wake(C.byref(RefRW(*map(float, rw))), float(t))
+
+
+def transverse_wake_table(resonators, grid):
+    arr = (RefResonator * max(1, len(resonators)))(*[RefResonator(*r) for r in resonators])
+    g = RefGrid(*grid)
+    T = np.zeros(g.nbins)
+    rc = lib().mbt_ref_transverse_wake_table(len(resonators), arr, C.byref(g), _dp(T))
+    if rc:
+        raise OracleError(rc, "transverse_wake_table")
+    return T
+
+
+def dipole_histogram(grid, tau, x):
+    g = RefGrid(*grid)
+    t = np.ascontiguousarray(tau, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    counts = np.zeros(g.nbins, dtype=np.uint32)
+    X = np.zeros(g.nbins)
+    rc = lib().mbt_ref_dipole_histogram(C.byref(g), t.size, _dp(t), _dp(xx), _up(counts), _dp(X))
+    if rc:
+        raise OracleError(rc, "dipole_histogram")
+    return counts, X
+
+
+def transverse_kicks(T, X, scale):
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    U = np.zeros_like(T)
+    rc = lib().mbt_ref_transverse_kicks(T.size, _dp(T), _dp(X), float(scale), _dp(U))
+    if rc:
+        raise OracleError(rc, "transverse_kicks")
+    return U
 
 
 def threads():
@@ -285,6 +352,70 @@ class RefSim:
         if phasors is not None and len(phasors):
             ph[:2 * self.n_lr] = np.asarray(phasors, dtype=np.float64)[:2 * self.n_lr]
         self._check(lib().mbt_ref_set_state(self._h, turn, seed, _dp(ph)))
+
+    # ---- transverse plane --------------------------------------------
+    def set_transverse(self, tr):
+        """tr: dict of RefTransverse fields, or None."""
+        if tr is None:
+            self._check(lib().mbt_ref_set_transverse(self._h, None))
+            self.tr = None
+            return
+        t = RefTransverse(**{k: float(v) for k, v in tr.items()})
+        self._check(lib().mbt_ref_set_transverse(self._h, C.byref(t)))
+        self.tr = dict(tr)
+
+    def set_transverse_wake(self, resonators):
+        arr = (RefResonator * max(1, len(resonators)))(*[RefResonator(*r) for r in resonators])
+        self._check(lib().mbt_ref_set_transverse_wake(self._h, len(resonators), arr))
+
+    def set_transverse_rw(self, rw):
+        """rw = (radius m, conductivity S/m, length m, turns), or None."""
+        if rw is None:
+            self._check(lib().mbt_ref_set_transverse_rw(self._h, None))
+            self.rw_turns = 0
+            return
+        r = RefLRRW(float(rw[0]), float(rw[1]), float(rw[2]), int(rw[3]))
+        self._check(lib().mbt_ref_set_transverse_rw(self._h, C.byref(r)))
+        self.rw_turns = int(rw[3])
+
+    def init_transverse(self, emittance, offset=0.0):
+        self._check(lib().mbt_ref_init_transverse(self._h, float(emittance), float(offset)))
+
+    def set_transverse_particles(self, bunch, x, xp):
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        b = np.ascontiguousarray(xp, dtype=np.float64)
+        assert a.size == self.N and b.size == self.N
+        self._check(lib().mbt_ref_set_transverse_particles(self._h, bunch, _dp(a), _dp(b)))
+
+    def get_transverse_particles(self, bunch):
+        x = np.zeros(self.N)
+        xp = np.zeros(self.N)
+        self._check(lib().mbt_ref_get_transverse_particles(self._h, bunch, _dp(x), _dp(xp)))
+        return x, xp
+
+    def track2(self, nturns, profiles_stride=0):
+        """Track; returns (moments [T][M][4], transverse moments [T][M][4]) and
+        the profiles when profiles_stride is given."""
+        mom = np.zeros((nturns, self.M, 4))
+        tmom = np.zeros((nturns, self.M, 4))
+        counts = None
+        if profiles_stride:
+            rows = -(-nturns // profiles_stride)
+            counts = np.zeros((rows, self.M, self.nbins), dtype=np.uint32)
+        self._check(lib().mbt_ref_track2(self._h, nturns, _dp(mom), _dp(tmom),
+                                         None if counts is None else _up(counts),
+                                         int(profiles_stride)))
+        return (mom, tmom, counts) if profiles_stride else (mom, tmom)
+
+    def get_rw_history(self):
+        H = np.zeros((self.rw_turns, self.M))
+        self._check(lib().mbt_ref_get_rw_history(self._h, _dp(H)))
+        return H
+
+    def set_rw_history(self, H):
+        h = np.ascontiguousarray(H, dtype=np.float64)
+        assert h.size == self.rw_turns * self.M
+        self._check(lib().mbt_ref_set_rw_history(self._h, _dp(h)))
 
     def derived(self):
         out = np.zeros(5)
