@@ -1,22 +1,33 @@
 #!/usr/bin/env python3
-"""Benchmark: macro-particle-turns/s of the plain FP64 GPU tracker on one MI355X.
+"""Benchmark: macro-particle-turns/s on one MI355X, the batched mixed-precision
+tracker against the plain FP64 tracker, plus p50/p99 job latency of the
+serving mix.
 
-Workload (default): the current-scan configuration -- eight single-bunch jobs
-of 1e6 macro-particles each (bunch currents 0.1-5 mA), 3rd-harmonic cavity at
-90% of its flat-potential voltage, broadband-resonator wake on 512 bins,
-run as one launch set per turn.  A step is one turn of the whole hot path
-(between-turn kernel: moments, wake potential; push kernel: kick, damping,
-noise, drift, histogram, deposits, moment sums; moment output).  Inputs are
-resident in HBM before the timed region.
+Headline workload (default): the full fill of the 484-bucket ring of the
+paper's Table 1 -- 484 bunches of 1e5 macro-particles at 1 mA, broadband
+resonator wake on 256 bins, one long-range higher-order-mode resonator.  Its
+particle state (774 MB) is three times the 256 MB Infinity Cache, so the push
+kernel streams from HBM.  A step is one turn of the whole hot path for every
+bunch: phasor scan; push (kick, damping, noise, drift, histogram, deposits,
+moment sums); between-turn kernel (moments, deposit sums, wake potential);
+moment output.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line with the throughput, the push kernel's roofline figures
-(algorithmic bytes per launch / average launch duration from HIP events over
-the timed region) and the oracle timed on the host cores.
+Two forms, each timed over exactly K turns after W warm-up turns:
+  batched_mixed (the `value`): a batch (captured 16-turn HIP graphs, push
+      launch shape tuned online during set-up), wake potential as a BF16x2
+      Toeplitz product on the matrix cores; FP64 coordinates and phasors;
+  plain_fp64: one job per launch set, eager launches, FP64 VALU convolution.
+The roofline of the push kernel comes from further turns whose every launch
+is bracketed by HIP events (outside the timed window).
+
+Prints one JSON line; progress goes to stderr as each part finishes.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -28,9 +39,15 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, vendor figure
 # instruction occupies a SIMD for four cycles), in lane-instructions/s.
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 BYTES_PER_PARTICLE_TURN = 32  # read tau, delta + write tau, delta (FP64)
-PMC_FILE = os.path.join(ROOT, "profiles", "push_c2_pmc.json")
+PMC_FILES = {"c2": os.path.join(ROOT, "profiles", "push_c2_pmc.json"),
+             "c4": os.path.join(ROOT, "profiles", "push_c4_pmc.json")}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1809_00391_amd", "csrc", f)
                for f in ("mbt_kernels.hip", "mbt_fastmath.h", "mbt_internal.h")]
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sha():
@@ -47,20 +64,22 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def pmc_record(particles_per_launch):
-    """The committed rocprofv3 counter record of the push (FETCH_SIZE and
-    WRITE_SIZE scaled by a copy kernel of known size, SQ instruction counts),
-    or None when it is missing or was taken on a different kernel source or
-    workload."""
-    if not os.path.exists(PMC_FILE):
+def pmc_record(key, particles_per_launch):
+    """The committed rocprofv3 counter record of the push on workload `key`
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size, SQ
+    instruction counts), or None when it is missing or was taken on a
+    different kernel source or workload."""
+    path = PMC_FILES.get(key)
+    if not path or not os.path.exists(path):
         return None
-    d = json.load(open(PMC_FILE))
+    d = json.load(open(path))
     if d.get("kernel_sha") != kernel_sha() or d.get("particles_per_launch") != particles_per_launch:
         return None
+    d["_path"] = path
     return d
 
 
-def make_tracker(w):
+def make_tracker(w, wake="fp64"):
     from paper_1809_00391_amd import tracker as tr
     t = tr.Tracker(w.ring)
     if w.hc_flat:
@@ -70,23 +89,120 @@ def make_tracker(w):
         t.set_short_range(list(w.short_range), w.grid)
     if w.long_range:
         t.set_long_range(list(w.long_range))
+    if wake != "fp64" and w.grid is not None:
+        t.set_wake_precision(wake)
     t.bind(w.N)
     t.init_gaussian(w.sigma_tau0, w.sigma_delta0, w.seed)
     return t
 
 
+def push_roofline(push_ms, push_n, particles, copy_gbs, pmc):
+    """Roofline figures of the push from HIP-event timings: algorithmic bytes
+    (32 B per macro-particle) per launch over the average launch duration."""
+    if not push_n:
+        return None
+    push_s = push_ms / 1e3 / push_n
+    gbs = BYTES_PER_PARTICLE_TURN * particles / push_s / 1e9
+    out = {"bound": "hbm", "kernel": "k_push", "achieved": gbs, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+           "traffic": pmc["hbm_bytes_per_launch"] if pmc else None,
+           "avg_launch_us": push_s * 1e6, "launches_timed": push_n,
+           "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles,
+           "copy_GBs": copy_gbs, "frac_of_copy": gbs / copy_gbs if copy_gbs else None}
+    if pmc:
+        lane_instr = pmc["valu_instructions_per_pair"] * particles / 2 / push_s
+        out["alu"] = {"bound": "alu",
+                      "valu_instructions_per_pair": pmc["valu_instructions_per_pair"],
+                      "achieved": lane_instr / 1e12, "peak": VALU_PEAK / 1e12,
+                      "unit": "T lane-instructions/s", "frac": lane_instr / VALU_PEAK,
+                      "source": os.path.relpath(pmc["_path"], ROOT)}
+    return out
+
+
+def run_form(w, key, form, steps, warmup, roofline_turns, wake, graph_turns, copy_gbs):
+    """Track workload w in one form: set-up, `warmup` untimed turns, exactly
+    `steps` timed turns (HIP events on the stream and the wall clock, the
+    larger counts), then `roofline_turns` turns with every launch bracketed."""
+    import torch
+    from paper_1809_00391_amd import tracker as tr
+    particles = w.M * w.N
+    t = make_tracker(w, wake if form == "batched_mixed" else "fp64")
+    b = None
+    if form == "batched_mixed":
+        b = tr.Batch([t], stream=t.stream, graph_turns=graph_turns, autotune=True)
+        run = lambda n: b.track(n, moments=True)
+        # set-up, untimed: the tuner times its launch-shape candidates on
+        # real turns (two per candidate), then the graph is captured
+        run(64 + 2 * graph_turns)
+    else:
+        run = lambda n: t.track(n, moments=True)
+    if warmup:
+        run(warmup)
+    stream = t.stream
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    mom = run(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    elapsed = max(wall, ev0.elapsed_time(ev1) / 1e3)
+    m = mom[0] if isinstance(mom, list) else mom
+    res = {"value": particles * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+           "moments_finite": bool(torch.isfinite(torch.from_numpy(m[-1])).all())}
+    if roofline_turns:
+        timer = b if b is not None else t
+        timer.set_timing(1)
+        run(roofline_turns)
+        torch.cuda.synchronize()
+        push_ms, push_n, btw_ms, btw_n = timer.get_timing()
+        timer.set_timing(0)
+        pmc = pmc_record(key, particles)
+        res["push_roofline"] = push_roofline(push_ms, push_n, particles, copy_gbs, pmc)
+        res["between_turn_us"] = btw_ms * 1e3 / btw_n if btw_n else None
+    if b is not None:
+        res.update({"wake": wake, "graph_turns": graph_turns, "autotune": True,
+                    "launch_groups": [list(g) for g in b.launch_info()]})
+        b.close()
+    else:
+        res.update({"wake": "fp64", "graph_turns": 0, "autotune": False})
+    t.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(w, budget_s):
-    """The oracle (as it stands) on this host's cores, on a bounded number of
-    turns of the same workload; then the same with one thread."""
+    """The oracle (as it stands) on this host's cores for a bounded number of
+    turns of the same workload (all bunches), then on one thread over the
+    first 44 of its bunches (a sample of the same per-bunch work)."""
     from oracle import ref
+    model, nproc = cpu_info()
     allc = ref.threads()
     out = _oracle_rate(w, budget_s)
     ref.set_threads(1)
     try:
-        one = _oracle_rate(w, budget_s / 3)
+        k = min(w.M, 44)
+        sub = w.with_(buckets=w.buckets[:k], currents_A=w.currents_A[:k])
+        one = _oracle_rate(sub, budget_s / 3)
     finally:
         ref.set_threads(allc)
     out["single_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    out["cpu_model"] = model
+    out["nproc"] = nproc
     return out
 
 
@@ -102,16 +218,16 @@ def _oracle_rate(w, budget_s):
         s.set_long_range(list(w.long_range))
     s.init_gaussian(w.N, w.sigma_tau0, w.sigma_delta0, w.seed)
     t0 = time.perf_counter()
-    s.track(2)
-    per_turn = (time.perf_counter() - t0) / 2
+    s.track(1)
+    per_turn = time.perf_counter() - t0
     turns = int(max(2, min(1000, budget_s / max(per_turn, 1e-9))))
     t0 = time.perf_counter()
     s.track(turns)
     dt = time.perf_counter() - t0
     return {"value": w.M * w.N * turns / dt, "unit": "macro-particle-turns/s",
             "cores": ref.threads(), "kind": "oracle",
-            "sample": f"{turns} turns of the same workload ({w.M} x {w.N} particles) after 2 "
-                      f"warm-up turns, {dt:.1f} s"}
+            "sample": f"{turns} turns of {w.M} bunches x {w.N} particles (same ring, wakes "
+                      f"and seed) after 1 warm-up turn, {dt:.1f} s"}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):
@@ -139,58 +255,15 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2 * nbytes / best / 1e9, ok
 
 
-def full_fill(turns, wake, copy_gbs=None):
-    """The full-fill configuration (484 bunches x 1e5 particles, BB wake on
-    256 bins, HOM long-range resonator) tracked `turns` turns twice: by the
-    plain FP64 tracker (eager launches, FP64 VALU convolution) and in the
-    batched mixed-precision form (captured 16-turn graphs, launch shape tuned
-    online, wake potential on the matrix cores in `wake`).  Moments are
-    copied out in both.  Returns both throughputs."""
-    import torch
-    from paper_1809_00391_amd import tracker as tr
+def cache_resident(turns, roofline_turns, copy_gbs):
+    """The eight-current scan (8 x 1e6 particles, 3rd-harmonic cavity, BB
+    wake on 512 bins) in the plain FP64 tracker.  Its 128 MB of state fits in
+    the 256 MB Infinity Cache, so its push fraction is not an HBM figure."""
     from paper_1809_00391_amd import workloads as wl
-    w = wl.PRESETS["c4"]
-    particles = w.M * w.N
-    res = {"workload": w.name, "turns_timed": turns, "unit": "macro-particle-turns/s"}
-    for form in ("plain_fp64", "batched_mixed"):
-        t = make_tracker(w)
-        b = None
-        if form == "batched_mixed":
-            t.set_wake_precision(wake)
-            b = tr.Batch([t], stream=t.stream, graph_turns=16, autotune=True)
-            run = lambda n: b.track(n, moments=True)
-        else:
-            run = lambda n: t.track(n, moments=True)
-        run(64)   # warm-up; the tuner measures its candidates here
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run(turns)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res[form] = {"value": particles * turns / dt, "ms_per_turn": dt * 1e3 / turns}
-        if b is None:
-            # this state (774 MB) is three times the Infinity Cache: the HBM
-            # case.  The push is timed on further turns, every one bracketed
-            # by HIP events, outside the throughput measurement above.
-            t.set_timing(1)
-            run(min(turns, 200))
-            torch.cuda.synchronize()
-            push_ms, push_n, _, _ = t.get_timing()
-            if push_n:
-                push_s = push_ms / 1e3 / push_n
-                gbs = BYTES_PER_PARTICLE_TURN * particles / push_s / 1e9
-                res[form]["push_roofline"] = {
-                    "bound": "hbm", "avg_launch_us": push_s * 1e6, "launches_timed": push_n,
-                    "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles, "achieved": gbs,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                    "frac_of_copy": gbs / copy_gbs if copy_gbs else None}
-        if b is not None:
-            res[form].update({"wake": wake, "graph_turns": 16, "autotune": True,
-                              "launch_groups": [list(g) for g in b.launch_info()]})
-            b.close()
-        t.close()
-        torch.cuda.empty_cache()
-    res["batched_over_plain"] = res["batched_mixed"]["value"] / res["plain_fp64"]["value"]
+    w = wl.PRESETS["c2"]
+    res = run_form(w, "c2", "plain_fp64", turns, 200, roofline_turns, "fp64", 0, copy_gbs)
+    res["workload"] = w.name
+    res["note"] = "state 128 MB, inside the 256 MB Infinity Cache: not an HBM measurement"
     return res
 
 
@@ -239,11 +312,11 @@ def paper_table4(turns):
 
 def serving_sample(scale, budget_gb, wake, fill):
     """The serving mix (64 jobs with Poisson arrivals at 2/s, bunch counts
-    {1, 3, 40, 121, 363, 484}, 1e4-2e5 particles, 1000-20000 turns) with turns
-    and arrival times scaled by `scale` so a sample takes seconds: once
-    through the continuous-batching server (matrix-core wake `wake`), once as
-    the plain per-job FP64 tracker running the jobs one after another in
-    arrival order.  Returns throughput and p50/p99 job latency of both."""
+    {1, 3, 40, 121, 363, 484}, 1e4-2e5 particles, 1000-20000 turns), with
+    turns and arrival times multiplied by `scale` (1.0: the mix as stated):
+    once through the continuous-batching server (matrix-core wake `wake`),
+    once as the plain per-job FP64 tracker running the jobs one after another
+    in arrival order.  Returns throughput and p50/p99 job latency of both."""
     import numpy as np
     import torch
     from paper_1809_00391_amd import serve
@@ -260,6 +333,7 @@ def serving_sample(scale, budget_gb, wake, fill):
     res = srv.run(reqs, keep_moments=False)
     span = time.perf_counter() - t0
     lat = serve.latency_percentiles(res)
+    progress(f"serving: batched form done ({span:.1f} s)")
     # plain FP64 tracker, one job at a time in arrival order
     t0 = time.perf_counter()
     done = []
@@ -272,43 +346,50 @@ def serving_sample(scale, budget_gb, wake, fill):
         trk.close()
         done.append(time.perf_counter() - t0 - r.arrival_s)
     span_plain = time.perf_counter() - t0
+    progress(f"serving: plain per-job form done ({span_plain:.1f} s)")
     return {"jobs": len(reqs), "scale": scale, "particle_turns": total,
+            "arrival_window_s": max(r.arrival_s for r in reqs),
             "batched": {"value": total / span, "p50_s": lat["p50"], "p99_s": lat["p99"],
-                        "wake": wake, "hbm_budget_gb": budget_gb, "fill_particles": fill,
-                        "slices": srv.slices,
-                        "batches_built": srv.batches_built, "peak_bytes": srv.peak_bytes},
-            "plain_fp64_per_job": {"value": total / span_plain,
+                        "span_s": span, "wake": wake, "hbm_budget_gb": budget_gb,
+                        "fill_particles": fill, "slices": srv.slices,
+                        "batches_built": srv.batches_built, "batch_build_s": srv.build_s,
+                        "peak_bytes": srv.peak_bytes},
+            "plain_fp64_per_job": {"value": total / span_plain, "span_s": span_plain,
                                    "p50_s": float(np.percentile(done, 50)),
                                    "p99_s": float(np.percentile(done, 99))},
+            "batched_over_plain": span_plain / span,
             "unit": "macro-particle-turns/s"}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000, help="timed turns")
-    ap.add_argument("--warmup", type=int, default=200, help="untimed turns first")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
-    ap.add_argument("--timing-every", type=int, default=32,
-                    help="bracket every k-th turn's launches with HIP events (each bracketed "
-                         "turn costs about 12 us of event records at c2; 0: none)")
+    ap.add_argument("--steps", type=int, default=2000, help="timed turns of each form")
+    ap.add_argument("--warmup", type=int, default=50, help="untimed turns of each form first")
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--wake", default="bf16x2", choices=["fp32", "bf16x2", "bf16x3"],
+                    help="matrix-core wake arithmetic of the batched form")
+    ap.add_argument("--graph-turns", type=int, default=16)
+    ap.add_argument("--roofline-turns", type=int, default=200,
+                    help="turns after the timed window with every push bracketed by HIP events")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0: skip)")
-    ap.add_argument("--serve-scale", type=float, default=0.05,
-                    help="turn and arrival-time scale of the serving sample (0: skip)")
+    ap.add_argument("--cache-resident-turns", type=int, default=2000,
+                    help="turns of the cache-resident eight-current scan (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="turn and arrival-time scale of the serving mix (1: as stated; 0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=24.0,
-                    help="HBM budget of the serving sample's admission")
-    ap.add_argument("--serve-wake", default="bf16x2", choices=["fp64", "fp32", "bf16x2", "bf16x3"])
+                    help="HBM budget of the serving admission")
     ap.add_argument("--serve-fill", type=float, default=3.2e7,
                     help="admit while the admitted jobs hold fewer particles than this (0: no limit)")
     ap.add_argument("--table4-turns", type=int, default=1000,
                     help="turns of the paper's Table 4 bunch counts (0: skip)")
-    ap.add_argument("--full-fill-turns", type=int, default=2000,
-                    help="turns of the full-fill plain vs batched comparison (0: skip)")
     ap.add_argument("--copy-bw", type=int, default=1,
                     help="measure the library copy kernel's bandwidth (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter scale for rocprofv3 --pmc)")
+    ap.add_argument("--forms", default="plain_fp64,batched_mixed",
+                    help="forms of the headline workload to run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -321,56 +402,32 @@ def main():
 
     w = wl.PRESETS[args.workload]
     torch.cuda.set_device(0)
-    t = make_tracker(w)
-    stream = t.stream
-    with torch.cuda.stream(stream):
-        if args.copy_probe:
-            a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-            b = torch.empty_like(a)
-            for _ in range(3):
-                b.copy_(a)
-            torch.cuda.synchronize()
-            del a, b
-        if args.warmup:
-            t.track(args.warmup, moments=True)
-        t.set_timing(args.timing_every)
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        wall0 = time.perf_counter()
-        ev0.record(stream)
-        mom = t.track(args.steps, moments=True)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
-    gpu_ms = ev0.elapsed_time(ev1)
-    elapsed = max(wall, gpu_ms / 1e3)
-    push_ms, push_n, _, _ = t.get_timing()
-    particles = w.M * w.N
-    value = particles * args.steps / elapsed
-    push_avg_s = push_ms / 1e3 / push_n if push_n else float("nan")
-    achieved = BYTES_PER_PARTICLE_TURN * particles / push_avg_s / 1e9 if push_n else float("nan")
-    pmc = pmc_record(particles)
-    traffic = pmc["hbm_bytes_per_launch"] if pmc else None
-    alu = None
-    if pmc and push_n:
-        lane_instr = pmc["valu_instructions_per_pair"] * particles / 2 / push_avg_s
-        alu = {"bound": "alu", "valu_instructions_per_pair": pmc["valu_instructions_per_pair"],
-               "achieved": lane_instr / 1e12, "peak": VALU_PEAK / 1e12,
-               "unit": "T lane-instructions/s", "frac": lane_instr / VALU_PEAK,
-               "source": "profiles/push_c2_pmc.json (SQ_INSTS_VALU of the same kernel source)"}
-    finite = bool(torch.isfinite(torch.from_numpy(mom[-1])).all())
+        del a, b
     copy_gbs, copy_ok = copy_bandwidth() if args.copy_bw else (None, None)
-
+    progress(f"copy bandwidth {copy_gbs}")
+    forms = {}
+    for form in args.forms.split(","):
+        forms[form] = run_form(w, args.workload, form, args.steps, args.warmup,
+                               args.roofline_turns, args.wake, args.graph_turns, copy_gbs)
+        progress(f"{form}: {forms[form]['value']:.4g} macro-particle-turns/s")
+    head = forms.get("batched_mixed") or forms[next(iter(forms))]
+    head_form = "batched_mixed" if "batched_mixed" in forms else next(iter(forms))
+    particles = w.M * w.N
     out = {
         "metric": "macro-particle-turns/s (FP64 plain vs batched mixed-prec) at 1 GPU; "
                   "p50/p99 job lat",
-        "value": value,
+        "value": head["value"],
         "unit": "macro-particle-turns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -378,33 +435,34 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": w.name,
-            "form": "plain FP64 tracker (one job per launch set, no graphs, no MFMA)",
+            "form": head_form,
             "bunches": w.M, "particles_per_bunch": w.N,
             "bins": w.grid[0] if w.grid else 0,
             "long_range_resonators": len(w.long_range),
             "turns_timed": args.steps,
+            "precision": ("FP64 coordinates, sums and long-range phasors; short-range wake "
+                          f"potential in {args.wake} on the matrix cores")
+                         if head_form == "batched_mixed" else "FP64 throughout",
         },
-        "roofline": {
-            "bound": "hbm", "kernel": "k_push",
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "avg_launch_us": push_avg_s * 1e6, "launches_timed": push_n,
-            "bytes_per_launch": BYTES_PER_PARTICLE_TURN * particles,
-            "alu": alu,
-            "copy_GBs": copy_gbs, "copy_exact": copy_ok,
-            "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
-        },
-        "moments_finite": finite,
+        "roofline": head.get("push_roofline"),
+        "forms": forms,
+        "moments_finite": all(f["moments_finite"] for f in forms.values()),
     }
+    if "batched_mixed" in forms and "plain_fp64" in forms:
+        out["batched_over_plain"] = forms["batched_mixed"]["value"] / forms["plain_fp64"]["value"]
+    out["copy_exact"] = copy_ok
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
-    if args.full_fill_turns > 0:
-        out["full_fill"] = full_fill(args.full_fill_turns, args.serve_wake, copy_gbs)
+        progress("cpu baseline done")
+    if args.cache_resident_turns > 0:
+        out["cache_resident"] = cache_resident(args.cache_resident_turns, args.roofline_turns,
+                                               copy_gbs)
+        progress("cache-resident scan done")
     if args.table4_turns > 0:
         out["paper_table4"] = paper_table4(args.table4_turns)
+        progress("table 4 done")
     if args.serve_scale > 0:
-        out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.serve_wake,
+        out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.wake,
                                         args.serve_fill or None)
     print(json.dumps(out), flush=True)
 

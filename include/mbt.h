@@ -331,6 +331,16 @@ int mbt_batch_configure(mbt_batch *batch, int32_t graph_turns, int32_t autotune)
 int mbt_batch_launch_info(const mbt_batch *batch, int32_t *ngroups, int32_t *nlr, int32_t *nsub,
                           int32_t *grid);
 
+/* Kernel timing of a batch, for measurement: as mbt_set_timing /
+ * mbt_get_timing, on the batch's stream.  The push total covers every push
+ * group of a bracketed turn; the between-turn total covers the phasor scan
+ * and the prep and wake kernels.  While every > 0 the batch issues its
+ * turns eagerly (a captured graph holds no events).  every = 0 switches
+ * timing off and clears the totals. */
+int mbt_batch_set_timing(mbt_batch *batch, int32_t every);
+int mbt_batch_get_timing(const mbt_batch *batch, double *push_ms, int64_t *push_launches,
+                         double *between_ms, int64_t *between_launches);
+
 /* Track nturns turns of every job.  out[j] (host [nturns][M_j], or NULL) and
  * counts[j] (host [ceil(nturns/stride[j])][M_j][nbins_j], or NULL) as in
  * mbt_track; out, counts and stride may themselves be NULL.  Blocks until

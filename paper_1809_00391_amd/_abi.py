@@ -95,6 +95,9 @@ SIGNATURES = {
     "mbt_batch_launch_info": (C.c_int, [C.c_void_p, _P(C.c_int32), C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "mbt_batch_track": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mbt_batch_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mbt_batch_get_timing": (C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64),
+                                       _P(C.c_double), _P(C.c_int64)]),
     "mbt_philox4x32_10": (C.c_int, [C.c_int64, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p,
                                     C.c_void_p]),
     "mbt_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),

@@ -1450,6 +1450,7 @@ struct mbt_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int exec_turns = 0, exec_phase = 0;  // captured turns and the phase of the first
+    Timer timer;  // measurement only: bracketed turns run eagerly, never from a graph
     char err[512] = "";
 };
 
@@ -1829,6 +1830,7 @@ void mbt_batch_destroy(mbt_batch *B)
             return;
         (void)hipStreamSynchronize(B->stream);
         drop_graph(B);
+        timer_free(B->timer);
         if (B->cap)
             (void)hipStreamDestroy(B->cap);
         if (B->pin_desc)
@@ -1852,6 +1854,32 @@ int mbt_batch_configure(mbt_batch *B, int32_t graph_turns, int32_t autotune)
         B->autotune = autotune == 1;
         return MBT_OK;
     });
+}
+
+int mbt_batch_set_timing(mbt_batch *B, int32_t every)
+{
+    return guarded(B, [&]() -> int {
+        if (!B || every < 0)
+            return MBT_EINVAL;
+        HIPCHK(B, timer_set(B->timer, every));
+        return MBT_OK;
+    });
+}
+
+int mbt_batch_get_timing(const mbt_batch *B, double *push_ms, int64_t *push_launches,
+                         double *between_ms, int64_t *between_launches)
+{
+    if (!B)
+        return MBT_EINVAL;
+    if (push_ms)
+        *push_ms = B->timer.ms[0];
+    if (push_launches)
+        *push_launches = B->timer.launches[0];
+    if (between_ms)
+        *between_ms = B->timer.ms[1];
+    if (between_launches)
+        *between_launches = B->timer.launches[1];
+    return MBT_OK;
 }
 
 int mbt_batch_launch_info(const mbt_batch *B, int32_t *ngroups, int32_t *nlr, int32_t *nsub,
@@ -1934,7 +1962,8 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
                 drop_graph(B);
         }
         // turns per graph: whole rings' worth of rows at most
-        int G = B->graph_turns;
+        // turns bracketed by timing events are launched eagerly
+        int G = B->timer.every > 0 ? 0 : B->graph_turns;
         for (int j = 0; j < nj && G > 0; ++j) {
             mbt_ctx *c = B->jobs[j];
             G = std::min(G, c->L.mom_slots);
@@ -1958,7 +1987,8 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
         for (; t < nturns; ++t) {
             if ((rc = batch_rings(B, t, 1, st.data())))
                 return rc;
-            HIPCHK(B, enqueue_turn(B->eng, (int)(t & 1), B->stream, nullptr));
+            const bool timed = B->timer.every > 0 && (t % B->timer.every) == 0;
+            HIPCHK(B, enqueue_turn(B->eng, (int)(t & 1), B->stream, timed ? &B->timer : nullptr));
         }
         for (mbt_ctx *c : B->jobs) {
             c->turn += nturns;
@@ -1966,6 +1996,7 @@ int mbt_batch_track(mbt_batch *B, int64_t nturns, mbt_moments *const *out,
             HIPCHK(B, ring_flush(c->prof, B->stream));
         }
         HIPCHK(B, hipStreamSynchronize(B->stream));
+        HIPCHK(B, timer_collect(B->timer));
         int bad = -1;
         for (int j = 0; j < nj; ++j) {
             mbt_ctx *c = B->jobs[j];

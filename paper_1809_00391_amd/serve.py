@@ -112,6 +112,7 @@ class Server:
         self.clock = clock
         self.slices = 0
         self.batches_built = 0
+        self.build_s = 0.0    # host time spent building batches (set-up, not tracking)
         self.peak_bytes = 0
 
     def run(self, requests, keep_moments=True):
@@ -155,8 +156,10 @@ class Server:
             if changed or batch is None:
                 if batch is not None:
                     batch.close()
+                tb = self.clock()
                 batch = tr.Batch([a[1] for a in active], graph_turns=self.graph_turns,
                                  autotune=self.autotune)
+                self.build_s += self.clock() - tb
                 self.batches_built += 1
             n = min(self.quantum, min(a[2] for a in active))
             moms = batch.track(n, moments=keep_moments)
@@ -164,7 +167,7 @@ class Server:
             done_t = self.clock() - t0
             finished = []
             for j, a in enumerate(active):
-                r, trk, rem, res = a
+                r, _, rem, res = a
                 if keep_moments:
                     res.moments.append(moms[j])
                 res.particle_turns += float(r.workload.M) * r.workload.N * n
@@ -180,8 +183,9 @@ class Server:
                 batch = None
                 for j in reversed(finished):
                     r, trk, _, _ = active.pop(j)
-                    trk.close()
+                    trk.close()  # frees the job's state and workspace
                     used -= sizes[r.job_id]
+                del trk, a  # no reference outlives the job's footprint
                 torch.cuda.synchronize()
         if batch is not None:
             batch.close()

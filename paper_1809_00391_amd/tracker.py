@@ -90,9 +90,13 @@ class Tracker:
         self.stream = None
 
     def close(self):
+        """Destroy the context (mbt_destroy drains its stream first), then
+        drop the device buffers it was bound to."""
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.mbt_destroy(self._h)
             self._h = C.c_void_p()
+        self.state = None
+        self.work = None
 
     def __del__(self):
         try:
@@ -276,9 +280,12 @@ class Batch:
         self.configure(graph_turns, autotune)
 
     def close(self):
+        """Destroy the batch (mbt_batch_destroy drains its stream first), then
+        drop its table memory."""
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.mbt_batch_destroy(self._h)
             self._h = C.c_void_p()
+        self.work = None
 
     def __del__(self):
         try:
@@ -292,6 +299,18 @@ class Batch:
 
     def configure(self, graph_turns=0, autotune=False):
         self._check(self._L.mbt_batch_configure(self._h, int(graph_turns), int(bool(autotune))))
+
+    def set_timing(self, every):
+        """Bracket every `every`-th turn's launches with HIP events (eager
+        launches while on; 0: off and totals cleared)."""
+        self._check(self._L.mbt_batch_set_timing(self._h, int(every)))
+
+    def get_timing(self):
+        """(push ms total, push launches timed, between-turn ms total, its launches)."""
+        a, b, c, d = C.c_double(), C.c_int64(), C.c_double(), C.c_int64()
+        self._check(self._L.mbt_batch_get_timing(self._h, C.byref(a), C.byref(b), C.byref(c),
+                                                 C.byref(d)))
+        return a.value, b.value, c.value, d.value
 
     def launch_info(self):
         """[(long-range count, sub-histograms, workgroups)] per push group."""

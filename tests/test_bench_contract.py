@@ -23,7 +23,8 @@ def test_bench_json_line(cuda):
     print("[gpu case] bench contract (miniature run)", flush=True)
     r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "64",
                         "--warmup", "8", "--cpu-budget", "1", "--serve-scale", "0.002",
-                        "--full-fill-turns", "16", "--table4-turns", "4"],
+                        "--cache-resident-turns", "16", "--roofline-turns", "20",
+                        "--table4-turns", "4"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -36,6 +37,11 @@ def test_bench_json_line(cuda):
     assert d["n_gpus"] == 1 and d["steps"] == 64 and d["warmup"] == 8
     assert d["value"] > 0 and d["dtype"] == "f64" and "workload" in d["config"]
     assert "model" not in d["config"]
+    # the headline is the full fill in the batched mixed-precision form, the
+    # plain FP64 tracker beside it
+    assert d["config"]["bunches"] == 484 and d["config"]["form"] == "batched_mixed"
+    assert d["value"] == d["forms"]["batched_mixed"]["value"]
+    assert d["forms"]["plain_fp64"]["value"] > 0 and d["batched_over_plain"] > 0
     rl = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rl, k
@@ -43,6 +49,8 @@ def test_bench_json_line(cuda):
     assert abs(rl["frac"] - rl["achieved"] / rl["peak"]) < 1e-12
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
-    assert d["full_fill"]["batched_mixed"]["value"] > 0
+    assert cb["nproc"] >= 1 and "cpu_model" in cb
+    assert rl["launches_timed"] >= 20
+    assert d["cache_resident"]["value"] > 0
     assert d["serving"]["batched"]["p99_s"] >= d["serving"]["batched"]["p50_s"]
     assert len(d["paper_table4"]["rows"]) == 7

@@ -45,3 +45,35 @@ def test_each_job_same_alone_and_in_mix(cuda, wake):
     lat = serve.latency_percentiles(res)
     print(f"[serving] wake={wake} slices={srv.slices} batches={srv.batches_built} "
           f"p50={lat['p50']:.3f}s p99={lat['p99']:.3f}s", flush=True)
+
+
+@pytest.mark.parametrize("wake,tol", [("fp64", 1e-9), ("bf16x2", 1e-4)])
+def test_served_jobs_match_oracle(cuda, wake, tol):
+    """Every job of a served mix (arrivals while others run, a budget that
+    forces waiting, slices of 16 turns) against the FP64 oracle tracking the
+    same job alone from the same seed: moments over its first 100 turns within
+    1e-9 of the bunch scale with the FP64 wake, within 1e-4 with the BF16x2
+    wake on the matrix cores (its element-wise error bound gives deviations of
+    order 1e-5 of the rms over 100 turns)."""
+    from helpers import make_oracle, moment_excess
+    reqs = []
+    for r in _mix():
+        w = r.workload.with_(turns=100)
+        reqs.append(serve.Request(r.job_id, r.arrival_s, w, 100))
+    sizes = sorted(serve.footprint(r.workload) for r in reqs)
+    budget = sum(sizes[-3:])
+    print(f"[gpu case] served mix vs oracle, wake={wake}", flush=True)
+    srv = serve.Server(hbm_budget=budget, quantum=16, graph_turns=4, autotune=False, wake=wake)
+    res = srv.run(reqs)
+    assert srv.batches_built >= 3
+    worst = 0.0
+    for r in reqs:
+        o = make_oracle(r.workload)
+        ref_m = o.track(r.turns)
+        got = res[r.job_id].moments
+        assert got.shape == ref_m.shape
+        err = moment_excess(got, ref_m)
+        worst = max(worst, err)
+        assert err <= tol, (r.job_id, err)
+    print(f"[serving vs oracle] wake={wake} worst moment deviation {worst:.2e} (bar {tol:g})",
+          flush=True)
