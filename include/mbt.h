@@ -201,6 +201,30 @@ int mbt_query_bytes(const mbt_ctx *ctx, int64_t N, size_t *state_bytes, size_t *
 int mbt_bind(mbt_ctx *ctx, int64_t N, void *d_state, size_t state_bytes, void *d_work,
              size_t work_bytes, void *hip_stream);
 
+/* Bind without allocating, for callers that cannot allocate device or
+ * pinned host memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  As mbt_bind, except that the workspace is
+ * the library's own static device array of MBT_STATIC_WORK_BYTES on the
+ * current device (held by each device the library runs on until the process
+ * ends), and no pinned host memory is taken: this call makes no hipMalloc,
+ * hipHostMalloc, hipFree or event creation (its tables are built in ordinary
+ * host memory), and mbt_track on the context copies moments and profiles
+ * straight into the caller's host arrays.  The caller still provides d_state
+ * (256-byte aligned, state_bytes from mbt_query_bytes).
+ *   - One static workspace per device, shared by every such binding there: a
+ *     later mbt_bind_static on the same device takes it over, and every call
+ *     that uses the earlier context's workspace then returns MBT_ESTATE until
+ *     that context is bound again.  Calls that overlap on one device (other
+ *     host threads, other streams) race on it.
+ *   - Binding clears the workspace, so nothing of a previous binding's
+ *     contents carries over.
+ *   - A context bound this way cannot join a batch (MBT_EINVAL).
+ *   - MBT_ENOSPC if the job's workspace (work_bytes of mbt_query_bytes)
+ *     exceeds MBT_STATIC_WORK_BYTES; MBT_EINVAL on a null or misaligned
+ *     d_state, as mbt_bind. */
+#define MBT_STATIC_WORK_BYTES (64u << 20)
+int mbt_bind_static(mbt_ctx *ctx, int64_t N, void *d_state, size_t state_bytes, void *hip_stream);
+
 /* Initial distribution: tau ~ N(0, sigma_tau_s), delta ~ N(0, sigma_delta)
  * per particle from one Box-Muller pair of Philox-4x32-10 with key = seed and
  * counter = (particle, stream ordinal, 0, 1).  Sets turn = 0, the seed, and

@@ -26,6 +26,7 @@ MBT_WAKE_FP64 = 0
 MBT_WAKE_FP32 = 1
 MBT_WAKE_BF16X2 = 2
 MBT_WAKE_BF16X3 = 3
+MBT_STATIC_WORK_BYTES = 64 << 20
 
 
 class Ring(C.Structure):
@@ -72,6 +73,7 @@ SIGNATURES = {
     "mbt_query_bytes": (C.c_int, [_ctx, C.c_int64, _P(C.c_size_t), _P(C.c_size_t)]),
     "mbt_bind": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
                            C.c_void_p]),
+    "mbt_bind_static": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mbt_init_gaussian": (C.c_int, [_ctx, C.c_double, C.c_double, C.c_uint64]),
     "mbt_set_particles": (C.c_int, [_ctx, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "mbt_get_particles": (C.c_int, [_ctx, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),

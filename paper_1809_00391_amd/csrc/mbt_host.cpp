@@ -24,6 +24,32 @@
 
 using namespace mbt;
 
+// ---- Static workspace of mbt_bind_static -----------------------------------
+// For callers that cannot allocate device memory: one array per device,
+// resident until the process ends.  Host code never takes its name as an
+// address (in host code it is only a stand-in for the device symbol): the
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and is kept in StaticWorkspace::ptr.
+static __device__ __align__(256) unsigned char scratch[MBT_STATIC_WORK_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticWorkspace {
+    std::mutex mu;
+    void *ptr[kMaxDevices] = {};           // device address of scratch, per device
+    const mbt_ctx *owner[kMaxDevices] = {};  // context bound to it last
+};
+
+StaticWorkspace &static_ws()
+{
+    static StaticWorkspace w;
+    return w;
+}
+
+}  // namespace
+
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586;
@@ -211,8 +237,12 @@ struct mbt_ctx {
     unsigned char *work = nullptr;
     hipStream_t stream_h = nullptr;
     int device = 0;
-    Mirror *mirror = nullptr;  // pinned
+    Mirror *mirror = nullptr;  // pinned (or plain_mirror for a static binding)
     RingOut mom, prof;         // pinned staging of the output rings
+    // mbt_bind_static: the workspace is the library's static array on `device`,
+    // the mirror is plain host memory and the rings copy straight out
+    bool static_ws = false;
+    Mirror plain_mirror{};
     // launch shape (neither changes a result bit)
     int nsub = 0, push_grid = 0;
     // arithmetic of the wake potential (WakeMode) and its tables
@@ -596,11 +626,13 @@ int begin_call(mbt_ctx *c, int prof_stride, hipStream_t s)
 
 // --- output rings --------------------------------------------------------
 
-int ring_alloc(mbt_ctx *c, RingOut &r, const void *dev, size_t row_bytes, int slots)
+int ring_alloc(mbt_ctx *c, RingOut &r, const void *dev, size_t row_bytes, int slots, bool pinned)
 {
     r.dev = reinterpret_cast<const unsigned char *>(dev);
     r.row_bytes = row_bytes;
     r.slots = slots;
+    if (!pinned)
+        return MBT_OK;  // no staging: rows go straight into the caller's array
     HIPCHK(c, hipHostMalloc((void **)&r.pin, (size_t)slots * row_bytes, hipHostMallocDefault));
     HIPCHK(c, hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
     // a flush adds at most two pieces after landing the previous ones, so
@@ -646,6 +678,22 @@ hipError_t ring_flush(RingOut &r, hipStream_t s)
 {
     if (!r.dst || r.written == r.flushed)
         return hipSuccess;
+    if (!r.pin) {
+        // no staging (static binding): copy the rows into the caller's host
+        // array directly, in stream order
+        for (int64_t row = r.flushed; row < r.written;) {
+            const int64_t slot = row & (r.slots - 1);
+            const int64_t n = std::min<int64_t>(r.written - row, r.slots - slot);
+            hipError_t e = hipMemcpyAsync(r.dst + (size_t)row * r.row_bytes,
+                                          r.dev + (size_t)slot * r.row_bytes,
+                                          (size_t)n * r.row_bytes, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess)
+                return e;
+            row += n;
+        }
+        r.flushed = r.written;
+        return hipSuccess;
+    }
     hipError_t e = ring_land(r);
     if (e != hipSuccess)
         return e;
@@ -734,15 +782,30 @@ hipError_t timer_collect(Timer &t)
     return hipSuccess;
 }
 
+// Whether c is the context last bound to its device's static workspace.
+bool owns_static(const mbt_ctx *c)
+{
+    StaticWorkspace &w = static_ws();
+    std::lock_guard<std::mutex> g(w.mu);
+    return c->device >= 0 && c->device < kMaxDevices && w.owner[c->device] == c;
+}
+
 void release_binding(mbt_ctx *c)
 {
     if (c->bound)
         (void)hipStreamSynchronize(c->stream_h);
     ring_free(c->mom);
     ring_free(c->prof);
-    if (c->mirror)
+    if (c->mirror && c->mirror != &c->plain_mirror)
         (void)hipHostFree(c->mirror);
     c->mirror = nullptr;
+    if (c->static_ws) {
+        StaticWorkspace &w = static_ws();
+        std::lock_guard<std::mutex> g(w.mu);
+        if (c->device >= 0 && c->device < kMaxDevices && w.owner[c->device] == c)
+            w.owner[c->device] = nullptr;
+        c->static_ws = false;
+    }
     c->bound = false;
 }
 
@@ -752,6 +815,28 @@ int need_bound(mbt_ctx *c)
         return MBT_EINVAL;
     if (!c->bound)
         return fail(c, MBT_ESTATE, "context not bound: call mbt_bind first");
+    if (c->static_ws && !owns_static(c))
+        return fail(c, MBT_ESTATE, "a later mbt_bind_static on device %d took the static workspace: "
+                    "bind this context again", c->device);
+    return MBT_OK;
+}
+
+// Device address of the static workspace on the current device, looked up
+// once per device (with that device current) and kept.
+int static_workspace(mbt_ctx *c, int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(c, MBT_EINVAL, "device %d beyond the static workspace table", device);
+    StaticWorkspace &w = static_ws();
+    std::lock_guard<std::mutex> g(w.mu);
+    if (!w.ptr[device]) {
+        void *p = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255))
+            return fail(c, MBT_EDEVICE, "static workspace address %p unusable", p);
+        w.ptr[device] = p;
+    }
+    *out = reinterpret_cast<unsigned char *>(w.ptr[device]);
     return MBT_OK;
 }
 
@@ -987,29 +1072,55 @@ int mbt_query_bytes(const mbt_ctx *c, int64_t N, size_t *state_bytes, size_t *wo
     });
 }
 
-int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_work,
-             size_t work_bytes, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// mbt_bind and mbt_bind_static.  With `st` the workspace is the current
+// device's static array (d_work and work_bytes are ignored), the host mirror
+// is plain memory and the output rings have no pinned staging.
+int bind_job(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_work,
+             size_t work_bytes, void *hip_stream, bool st)
 {
-    return guarded(c, [&]() -> int {
+    {
         if (!c)
             return MBT_EINVAL;
         if (c->M < 1)
             return fail(c, MBT_ESTATE, "fill not set");
         if (N < 1 || N > ((int64_t)1 << 32))
             return fail(c, MBT_EINVAL, "N must be in [1, 2^32]");
-        if (!d_state || !d_work || ((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
+        if (!d_state || ((uintptr_t)d_state & 255) || (!st && (!d_work || ((uintptr_t)d_work & 255))))
             return fail(c, MBT_EINVAL, "device buffers must be non-null and 256-byte aligned");
         Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
-        if (state_bytes < L.state_bytes || work_bytes < L.total)
+        if (st && L.total > (size_t)MBT_STATIC_WORK_BYTES)
+            return fail(c, MBT_ENOSPC, "the job needs %zu workspace bytes; the static workspace "
+                        "holds %zu", L.total, (size_t)MBT_STATIC_WORK_BYTES);
+        if (state_bytes < L.state_bytes || (!st && work_bytes < L.total))
             return fail(c, MBT_ENOSPC, "need %zu state and %zu workspace bytes", L.state_bytes, L.total);
+        int device = 0;
+        HIPCHK(c, hipGetDevice(&device));
+        unsigned char *work = reinterpret_cast<unsigned char *>(d_work);
+        if (st) {
+            int rc = static_workspace(c, device, &work);
+            if (rc)
+                return rc;
+        }
         release_binding(c);
         c->L = L;
         c->N = N;
         c->tau = reinterpret_cast<double *>(d_state);
         c->delta = c->tau + (size_t)c->M * L.ld;
-        c->work = reinterpret_cast<unsigned char *>(d_work);
+        c->work = work;
         c->stream_h = reinterpret_cast<hipStream_t>(hip_stream);
-        HIPCHK(c, hipGetDevice(&c->device));
+        c->device = device;
+        if (st) {
+            // from here on this context owns the device's static workspace;
+            // an earlier owner gets MBT_ESTATE until it is bound again
+            StaticWorkspace &w = static_ws();
+            std::lock_guard<std::mutex> g(w.mu);
+            w.owner[device] = c;
+            c->static_ws = true;
+        }
 
         const int M = c->M, nb = c->nbins(), nbx = std::max(nb, 1), nlr = c->nlr();
         // Host-side tables.
@@ -1112,11 +1223,15 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
                                  hipMemcpyHostToDevice, c->stream_h));
         HIPCHK(c, hipMemsetAsync(d_state, 0, L.state_bytes, c->stream_h));
         HIPCHK(c, hipStreamSynchronize(c->stream_h));
-        HIPCHK(c, hipHostMalloc((void **)&c->mirror, sizeof(Mirror), hipHostMallocDefault));
-        int rc = ring_alloc(c, c->mom, c->w<double>(L.mom), (size_t)M * sizeof(mbt_moments), L.mom_slots);
+        if (st)
+            c->mirror = &c->plain_mirror;
+        else
+            HIPCHK(c, hipHostMalloc((void **)&c->mirror, sizeof(Mirror), hipHostMallocDefault));
+        int rc = ring_alloc(c, c->mom, c->w<double>(L.mom), (size_t)M * sizeof(mbt_moments),
+                            L.mom_slots, !st);
         if (!rc)
             rc = ring_alloc(c, c->prof, c->w<uint32_t>(L.prof), (size_t)M * nbx * sizeof(uint32_t),
-                            L.prof_slots);
+                            L.prof_slots, !st);
         if (rc) {
             release_binding(c);
             return rc;
@@ -1130,6 +1245,25 @@ int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
         c->dirty = true;
         c->turn = 0;
         return MBT_OK;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbt_bind(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_work,
+             size_t work_bytes, void *hip_stream)
+{
+    return guarded(c, [&]() -> int {
+        return bind_job(c, N, d_state, state_bytes, d_work, work_bytes, hip_stream, false);
+    });
+}
+
+int mbt_bind_static(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *hip_stream)
+{
+    return guarded(c, [&]() -> int {
+        return bind_job(c, N, d_state, state_bytes, nullptr, 0, hip_stream, true);
     });
 }
 
@@ -1286,7 +1420,7 @@ int mbt_wake_table(const mbt_ctx *c, double *W)
     return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
         if (!c || !W)
             return MBT_EINVAL;
-        if (!c->bound || !c->sr_on)
+        if (!c->bound || !c->sr_on || (c->static_ws && !owns_static(c)))
             return MBT_ESTATE;
         if (hipMemcpy(W, c->w<double>(c->L.W), (size_t)c->nbins() * sizeof(double),
                       hipMemcpyDeviceToHost) != hipSuccess)
@@ -1703,9 +1837,12 @@ int mbt_batch_query_bytes(mbt_ctx *const *jobs, int32_t njobs, size_t *work_byte
     return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
         if (!jobs || njobs < 1 || njobs > 65535 || !work_bytes)
             return MBT_EINVAL;
-        for (int j = 0; j < njobs; ++j)
+        for (int j = 0; j < njobs; ++j) {
             if (!jobs[j] || !jobs[j]->bound)
                 return MBT_ESTATE;
+            if (jobs[j]->static_ws)
+                return MBT_EINVAL;  // the static workspace is not a batch job's own
+        }
         size_t a, b, w;
         *work_bytes = batch_layout(jobs, njobs, &a, &b, &w);
         return MBT_OK;

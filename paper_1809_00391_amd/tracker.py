@@ -166,6 +166,18 @@ class Tracker:
                                      C.c_void_p(self.stream.cuda_stream)))
         self.N = int(N)
 
+    def bind_static(self, N, device="cuda", stream=None):
+        """mbt_bind_static: allocate only the particle state (a torch tensor)
+        and bind it with the library's static workspace on the device."""
+        sb, _ = self.query_bytes(N)
+        self.state = torch.empty(sb + 256, dtype=torch.uint8, device=device)
+        self.work = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.state.device)
+        sp = (self.state.data_ptr() + 255) & ~255
+        self._check(self._L.mbt_bind_static(self._h, int(N), C.c_void_p(sp), sb,
+                                            C.c_void_p(self.stream.cuda_stream)))
+        self.N = int(N)
+
     # ---- particles and state -------------------------------------------
     def init_gaussian(self, sigma_tau_s, sigma_delta, seed):
         self._check(self._L.mbt_init_gaussian(self._h, float(sigma_tau_s), float(sigma_delta),

@@ -104,6 +104,38 @@ def test_call_order_and_argument_errors():
     L.mbt_destroy(h)
 
 
+def test_static_bind_rejects_before_device_work():
+    """mbt_bind_static checks its arguments and the job's workspace against
+    MBT_STATIC_WORK_BYTES before touching the device."""
+    L, h, rc = _ctx()
+    fake = C.c_void_p(1 << 20)
+    assert L.mbt_bind_static(h, 1000, fake, 1 << 30, None) == _abi.MBT_ESTATE  # no fill
+    b = (C.c_int32 * 2)(0, 5)
+    cur = (C.c_double * 2)(1e-3, 1e-3)
+    assert L.mbt_set_fill(h, 2, b, cur, None) == 0
+    sb, wb = C.c_size_t(), C.c_size_t()
+    assert L.mbt_query_bytes(h, 1000, C.byref(sb), C.byref(wb)) == 0
+    assert wb.value <= _abi.MBT_STATIC_WORK_BYTES
+    assert L.mbt_bind_static(h, 1000, None, sb.value, None) == _abi.MBT_EINVAL
+    assert L.mbt_bind_static(h, 1000, C.c_void_p((1 << 20) + 8), sb.value, None) == _abi.MBT_EINVAL
+    assert L.mbt_bind_static(h, 1000, fake, sb.value - 8, None) == _abi.MBT_ENOSPC
+    L.mbt_destroy(h)
+    # a job whose tables, histograms and output rings exceed the static array
+    big = 4000
+    L, h, rc = _ctx(dict(wl.RING_R480, harmonic=big))
+    bk = (C.c_int32 * big)(*range(big))
+    cu = (C.c_double * big)(*([1e-3] * big))
+    assert L.mbt_set_fill(h, big, bk, cu, None) == 0
+    g = _abi.Grid(4096, -1e-10, 1e-10)
+    res = (_abi.Resonator * 1)(_abi.Resonator(1e4, 1.0, 2e10))
+    assert L.mbt_set_short_range(h, 1, res, C.byref(g)) == 0
+    assert L.mbt_query_bytes(h, 1000, C.byref(sb), C.byref(wb)) == 0
+    assert wb.value > _abi.MBT_STATIC_WORK_BYTES
+    assert L.mbt_bind_static(h, 1000, fake, sb.value, None) == _abi.MBT_ENOSPC
+    assert b"static workspace" in L.mbt_last_error(h)
+    L.mbt_destroy(h)
+
+
 def test_hc_flat_fraction_agrees_with_oracle():
     from oracle import ref
     for frac in (0.5, 0.9, 1.0):
