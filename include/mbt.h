@@ -178,6 +178,103 @@ int mbt_set_short_range(mbt_ctx *ctx, int32_t nres, const mbt_resonator *res,
  * Must precede mbt_bind. */
 int mbt_set_resistive_wall(mbt_ctx *ctx, const mbt_resistive_wall *rw);
 
+/* ---- Transverse plane ------------------------------------------------------
+ * One transverse plane (x in m, x' in rad) tracked beside (tau, delta): the
+ * betatron map of Sec. 2.2 (Eqs. 3-5), the transverse wake kick of Sec. 2.3
+ * (Eq. 6, second line) and the long-range resistive wall applied after all
+ * bunches of a turn (Sec. 2.3, last paragraph).  The longitudinal map is
+ * unchanged.  Per turn and particle, in this order, with delta and tau the
+ * values before this turn's kick and k the bin of tau:
+ *   x' += the bunch's long-range resistive-wall kick (from the passages of
+ *         the previous turn and the turns before it, see below);
+ *   x' += U[k]  (the bin's transverse wake kick; none outside the grid);
+ *   xb = x - D delta, xb' = x' - D' delta, psi = 2 pi (frac(Q) + Q' delta),
+ *   x  <- D delta  + (cos psi + alpha sin psi) xb + beta sin psi xb',
+ *   x' <- D' delta - gamma sin psi xb + (cos psi - alpha sin psi) xb'
+ *         (rotation about the dispersive orbit, gamma = (1 + alpha^2)/beta);
+ *   x' *= (1 + delta) / (1 + delta + e_rf/E0)  (adiabatic damping across the
+ *         energy gain e_rf of the main and harmonic cavities);
+ *   x += sqrt(eps beta D_x) z, x' += sqrt(eps gamma D_x) z', D_x =
+ *         2 T0 / tau_damp, z and z' from Philox counters (particle/2, stream
+ *         ordinal, turn, 2) and (particle/2, stream ordinal, turn, 3), the
+ *         pair's cosine branch for even particles, its sine branch for odd.
+ * U[k] = (q_pp / E0) sum_{m<k} T[k-m] X[m]: T[j] the summed transverse wake
+ * of the resonators at bin distance j (T[0] = 0), X[m] the sum of x over the
+ * particles in bin m (the bin's dipole moment times its count).  X is summed
+ * as an exact integer multiple of 2^-52 m after rounding each x to that grid
+ * (at most 1.1e-16 m per particle), so it does not depend on the order of
+ * the particles; |X| of a bin must stay below 2^11 m.
+ * Jobs with the plane compute their longitudinal wake in FP64 (the
+ * matrix-core modes return MBT_EINVAL) and cannot join a batch.
+ *
+ * The plane, its wake and its wall are set before mbt_bind; NULL switches
+ * each off.  MBT_EINVAL on beta <= 0, eps < 0, tau_damp <= 0 or a non-finite
+ * value. */
+typedef struct {
+    double tune;          /* betatron tune Q; only frac(Q) enters              */
+    double chromaticity;  /* Q': phase advance 2 pi (frac(Q) + Q' delta)       */
+    double alpha;         /* Twiss alpha at the observation point              */
+    double beta_m;        /* Twiss beta > 0                                    */
+    double disp_m;        /* dispersion D                                      */
+    double disp_prime;    /* dispersion slope D'                               */
+    double emittance_m;   /* equilibrium emittance eps >= 0 (noise scale)      */
+    double tau_damp_s;    /* amplitude damping time > 0; +inf or eps 0: no noise */
+} mbt_transverse;
+int mbt_set_transverse(mbt_ctx *ctx, const mbt_transverse *tr);
+
+/* Transverse short-range resonators (R_s in Ohm/m), on the short-range grid:
+ * W_T(t) = (R_s w_r^2 / (Q wbar)) exp(-alpha t) sin(wbar t) for t > 0.
+ * nres <= MBT_MAX_SHORT_RANGE; acts only with a grid. */
+int mbt_set_transverse_wake(mbt_ctx *ctx, int32_t nres, const mbt_resonator *res);
+
+/* Long-range transverse resistive wall of a round pipe (thick wall,
+ * W_T(t) = (L / (pi b^3)) sqrt(Z0 c / (pi sigma t))): each bunch b gets, at
+ * the start of turn n, the kick (1/E0) sum I_b' T0 <x>_b' W_T(t) over the
+ * passages of bunches b' < b in turn n - 1 and of every bunch in turns
+ * n - K .. n - 2 (turns >= 0), each a rigid dipole of charge I_b' T0 at its
+ * centroid <x>_b' after that turn, t the time from that passage to bunch b's
+ * passage in turn n - 1.  Cost K M^2 terms per turn. */
+typedef struct {
+    double radius_m;
+    double conductivity_S_m;
+    double length_m;
+    int32_t turns;        /* K, 1 .. 1024 */
+} mbt_transverse_rw;
+int mbt_set_transverse_rw(mbt_ctx *ctx, const mbt_transverse_rw *rw);
+
+/* Matched Gaussian betatron coordinates for every particle: x = offset +
+ * sqrt(eps beta) z0, x' = sqrt(eps / beta) (z1 - alpha z0), (z0, z1) one
+ * Box-Muller pair of Philox with key = the seed in force (mbt_init_gaussian
+ * or mbt_set_state) and counter (particle, stream ordinal, 0, 4).  Clears
+ * the wall's centroid history.  MBT_ESTATE without the plane or binding. */
+int mbt_init_transverse(mbt_ctx *ctx, double emittance_m, double offset_m);
+
+/* Copy N transverse coordinates of a bunch in or out (as mbt_set_particles /
+ * mbt_get_particles; x' as stored, before any pending wall kick). */
+int mbt_set_transverse_particles(mbt_ctx *ctx, int32_t bunch, const double *x, const double *xp,
+                                 int32_t where);
+int mbt_get_transverse_particles(mbt_ctx *ctx, int32_t bunch, double *x, double *xp,
+                                 int32_t where);
+
+/* Per-bunch transverse statistics after a turn (Sec. 2.4). */
+typedef struct {
+    double mean_x;
+    double mean_xp;
+    double rms_x;
+    double rms_xp;
+} mbt_tmoments;
+
+/* As mbt_track, plus tout: host array [nturns][M] of transverse moments
+ * after each turn (may be NULL; MBT_EINVAL if not NULL without the plane). */
+int mbt_track2(mbt_ctx *ctx, int64_t nturns, mbt_moments *out, mbt_tmoments *tout,
+               uint32_t *counts, int32_t stride);
+
+/* Wall history for a checkpoint: bunch centroids <x> of the last K turns,
+ * [K][M], row r holding turn t with t mod K == r (zeros for turns never
+ * tracked).  MBT_ESTATE without a wall or binding. */
+int mbt_get_rw_history(mbt_ctx *ctx, double *H);
+int mbt_set_rw_history(mbt_ctx *ctx, const double *H);
+
 /* Long-range resonators (Sec. 4 higher-order mode): each acts on later
  * bunch passages through a complex phasor rotated bucket to bucket; its
  * same-bunch same-turn part acts through the short-range table, to which it
@@ -228,7 +325,8 @@ int mbt_bind_static(mbt_ctx *ctx, int64_t N, void *d_state, size_t state_bytes, 
 /* Initial distribution: tau ~ N(0, sigma_tau_s), delta ~ N(0, sigma_delta)
  * per particle from one Box-Muller pair of Philox-4x32-10 with key = seed and
  * counter = (particle, stream ordinal, 0, 1).  Sets turn = 0, the seed, and
- * clears the long-range phasors.  Asynchronous on the bound stream. */
+ * clears the long-range phasors; with the transverse plane also x = x' = 0
+ * and the wall's history.  Asynchronous on the bound stream. */
 int mbt_init_gaussian(mbt_ctx *ctx, double sigma_tau_s, double sigma_delta, uint64_t seed);
 
 /* Copy N coordinates of bunch `bunch` in (where == MBT_HOST: host arrays,

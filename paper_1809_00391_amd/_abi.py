@@ -52,6 +52,22 @@ class ResistiveWall(C.Structure):
                 ("length_m", C.c_double)]
 
 
+class Transverse(C.Structure):
+    _fields_ = [("tune", C.c_double), ("chromaticity", C.c_double), ("alpha", C.c_double),
+                ("beta_m", C.c_double), ("disp_m", C.c_double), ("disp_prime", C.c_double),
+                ("emittance_m", C.c_double), ("tau_damp_s", C.c_double)]
+
+
+class TransverseRW(C.Structure):
+    _fields_ = [("radius_m", C.c_double), ("conductivity_S_m", C.c_double),
+                ("length_m", C.c_double), ("turns", C.c_int32)]
+
+
+class TMoments(C.Structure):
+    _fields_ = [("mean_x", C.c_double), ("mean_xp", C.c_double), ("rms_x", C.c_double),
+                ("rms_xp", C.c_double)]
+
+
 class Moments(C.Structure):
     _fields_ = [("mean_tau", C.c_double), ("mean_delta", C.c_double),
                 ("rms_tau", C.c_double), ("rms_delta", C.c_double)]
@@ -70,6 +86,17 @@ SIGNATURES = {
     "mbt_set_short_range": (C.c_int, [_ctx, C.c_int32, _P(Resonator), _P(Grid)]),
     "mbt_set_long_range": (C.c_int, [_ctx, C.c_int32, _P(Resonator)]),
     "mbt_set_resistive_wall": (C.c_int, [_ctx, _P(ResistiveWall)]),
+    "mbt_set_transverse": (C.c_int, [_ctx, _P(Transverse)]),
+    "mbt_set_transverse_wake": (C.c_int, [_ctx, C.c_int32, _P(Resonator)]),
+    "mbt_set_transverse_rw": (C.c_int, [_ctx, _P(TransverseRW)]),
+    "mbt_init_transverse": (C.c_int, [_ctx, C.c_double, C.c_double]),
+    "mbt_set_transverse_particles": (C.c_int, [_ctx, C.c_int32, C.c_void_p, C.c_void_p,
+                                               C.c_int32]),
+    "mbt_get_transverse_particles": (C.c_int, [_ctx, C.c_int32, C.c_void_p, C.c_void_p,
+                                               C.c_int32]),
+    "mbt_track2": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "mbt_get_rw_history": (C.c_int, [_ctx, C.c_void_p]),
+    "mbt_set_rw_history": (C.c_int, [_ctx, C.c_void_p]),
     "mbt_query_bytes": (C.c_int, [_ctx, C.c_int64, _P(C.c_size_t), _P(C.c_size_t)]),
     "mbt_bind": (C.c_int, [_ctx, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
                            C.c_void_p]),

@@ -112,13 +112,16 @@ constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS of one push workgroup
 struct Layout {
     size_t desc, items_push, items_prep, items_wake, clock, status, Wbf, Wf32;
     size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, mom, prof;
+    // transverse plane (empty regions without it)
+    size_t Tt, U, Xq, tmom, H, rwk, bucket, qb;
     size_t total;
     int mom_slots, prof_slots, ntiles, ppt, nchunks, nwake, conv_out;
     int64_t ld;
     size_t state_bytes;
 };
 
-Layout make_layout(int M, int64_t N, int nb, int nlr)
+// tr: the job tracks a transverse plane; rw_turns: K of its wall (0: none).
+Layout make_layout(int M, int64_t N, int nb, int nlr, bool tr = false, int rw_turns = 0)
 {
     Layout L{};
     const int nbx = std::max(nb, 1);
@@ -162,8 +165,17 @@ Layout make_layout(int M, int64_t N, int nb, int nlr)
     L.stream = take((size_t)M * sizeof(uint32_t));
     L.mom = take((size_t)L.mom_slots * moment_row);
     L.prof = take((size_t)L.prof_slots * prof_row);
+    const size_t ntr = tr ? 1 : 0;
+    L.Tt = take(ntr * nbx * sizeof(double));
+    L.U = take(ntr * M * nbx * sizeof(double));
+    L.Xq = take(ntr * 2 * M * nbx * sizeof(unsigned long long));
+    L.tmom = take(ntr * L.mom_slots * moment_row);
+    L.H = take(ntr * (size_t)rw_turns * M * sizeof(double));
+    L.rwk = take(ntr * M * sizeof(double));
+    L.bucket = take(ntr * M * sizeof(int32_t));
+    L.qb = take(ntr * M * sizeof(double));
     L.total = o;
-    L.state_bytes = (size_t)2 * M * (size_t)L.ld * sizeof(double);
+    L.state_bytes = (size_t)(tr ? 4 : 2) * M * (size_t)L.ld * sizeof(double);
     return L;
 }
 
@@ -229,16 +241,22 @@ struct mbt_ctx {
     std::vector<Resonator> sr, lr;
     bool rw_on = false;
     ResistiveWall rw{};
+    // transverse plane, its short-range resonators (R_s in Ohm/m) and wall
+    bool tr_on = false;
+    mbt_transverse tr{};
+    std::vector<Resonator> tw;
+    bool trw_on = false;
+    mbt_transverse_rw trw{};
     // binding
     bool bound = false;
     int64_t N = 0;
     Layout L{};
-    double *tau = nullptr, *delta = nullptr;
+    double *tau = nullptr, *delta = nullptr, *x = nullptr, *xp = nullptr;
     unsigned char *work = nullptr;
     hipStream_t stream_h = nullptr;
     int device = 0;
     Mirror *mirror = nullptr;  // pinned (or plain_mirror for a static binding)
-    RingOut mom, prof;         // pinned staging of the output rings
+    RingOut mom, prof, tmom;   // pinned staging of the output rings
     // mbt_bind_static: the workspace is the library's static array on `device`,
     // the mirror is plain host memory and the rings copy straight out
     bool static_ws = false;
@@ -260,6 +278,11 @@ struct mbt_ctx {
     template <class T> T *w(size_t off) const { return reinterpret_cast<T *>(work + off); }
     int nbins() const { return sr_on ? grid.nbins : 0; }
     int nlr() const { return (int)lr.size(); }
+    int rw_turns() const { return tr_on && trw_on ? trw.turns : 0; }
+    Layout layout(int64_t n) const
+    {
+        return make_layout(M, n, nbins(), nlr(), tr_on, rw_turns());
+    }
 };
 
 struct mbt_batch;
@@ -392,6 +415,41 @@ JobDesc job_desc(const mbt_ctx *c, uint32_t base, int prof_stride)
     d.status = c->w<uint32_t>(c->L.status);
     d.clock = c->w<uint32_t>(c->L.clock);
     d.conv_out = c->L.conv_out;
+    d.tr_on = c->tr_on ? 1 : 0;
+    if (c->tr_on) {
+        const mbt_transverse &t = c->tr;
+        TransConst &tc = d.t;
+        tc.qfrac = t.tune - std::floor(t.tune);  // exact
+        tc.chrom = t.chromaticity;
+        tc.alpha = t.alpha;
+        tc.beta = t.beta_m;
+        tc.gamma = (1.0 + t.alpha * t.alpha) / t.beta_m;
+        tc.disp = t.disp_m;
+        tc.disp_p = t.disp_prime;
+        // Eq. 5: noise sigma sqrt(D_x) with D_x = 2 T0 / tau_damp
+        const double dx = 2.0 * c->T0 / t.tau_damp_s;
+        tc.noise_x = std::sqrt(t.emittance_m * t.beta_m) * std::sqrt(dx);
+        tc.noise_xp = std::sqrt(t.emittance_m * tc.gamma) * std::sqrt(dx);
+        tc.noise_on = (tc.noise_x > 0.0 || tc.noise_xp > 0.0) ? 1 : 0;
+        tc.rw_turns = c->rw_turns();
+        if (tc.rw_turns > 0) {
+            const double z0 = 376.730313668, cl = 299792458.0, rb = c->trw.radius_m;
+            tc.rw_amp = c->trw.length_m / (kPi * rb * rb * rb);
+            tc.rw_arg = z0 * cl / (kPi * c->trw.conductivity_S_m);
+        }
+        tc.T0 = c->T0;
+        tc.T_rf = c->T_rf;
+        d.x = c->x;
+        d.xp = c->xp;
+        d.Tt = c->w<double>(c->L.Tt);
+        d.U = c->w<double>(c->L.U);
+        d.Xq = c->w<unsigned long long>(c->L.Xq);
+        d.tmom_ring = c->w<double>(c->L.tmom);
+        d.H = c->w<double>(c->L.H);
+        d.rwk = c->w<double>(c->L.rwk);
+        d.bucket = c->w<int32_t>(c->L.bucket);
+        d.qb = c->w<double>(c->L.qb);
+    }
     return d;
 }
 
@@ -459,6 +517,10 @@ struct Engine {
     const uint32_t *one_clock = nullptr;
     std::vector<Group> groups;
     std::vector<WakeGroup> wakes;  // jobs whose wake potential comes from k_wake
+    // a single job with the transverse plane (batches hold none): its M and
+    // whether its long-range wall needs the kick kernel after the prep
+    bool tr = false, rw = false;
+    int tr_M = 0;
 };
 
 PushLaunch push_launch(const Engine &e, const Group &g, int phase)
@@ -488,7 +550,8 @@ void set_one_job(Engine &e, const mbt_ctx *c)
 hipError_t enqueue_push(const Engine &e, bool push, int phase, hipStream_t s)
 {
     for (const Group &g : e.groups) {
-        hipError_t r = launch_push(push_launch(e, g, phase), push, s);
+        const PushLaunch l = push_launch(e, g, phase);
+        hipError_t r = e.tr ? launch_push_tr(l, push, s) : launch_push(l, push, s);
         if (r != hipSuccess)
             return r;
     }
@@ -507,7 +570,16 @@ hipError_t enqueue_prep(const Engine &e, int phase, hipStream_t s)
     l.nbins_max = e.nbins_max;
     l.inner = e.one_chunks;
     l.clk = e.one_clock;
+    l.tr = e.tr ? 1 : 0;
     hipError_t r = e.nprep > 0 ? launch_prep(l, s) : hipSuccess;
+    if (r == hipSuccess && e.rw) {
+        RwLaunch w{};
+        w.phase = phase;
+        w.job = e.jobs;
+        w.M = e.tr_M;
+        w.clk = e.one_clock;
+        r = launch_rw(w, s);
+    }
     for (const WakeGroup &g : e.wakes) {
         if (r != hipSuccess)
             break;
@@ -590,6 +662,9 @@ Engine single_engine(const mbt_ctx *c)
         e.wakes.push_back(w);
     }
     set_one_job(e, c);
+    e.tr = c->tr_on;
+    e.rw = c->rw_turns() > 0;
+    e.tr_M = c->M;
     return e;
 }
 
@@ -617,6 +692,9 @@ int begin_call(mbt_ctx *c, int prof_stride, hipStream_t s)
     const int nbx = std::max(c->nbins(), 1);
     uint32_t *cnt = c->w<uint32_t>(c->L.counts) + (size_t)(c->turn & 1) * c->M * nbx;
     HIPCHK(c, hipMemsetAsync(cnt, 0, (size_t)c->M * nbx * sizeof(uint32_t), s));
+    if (c->tr_on)
+        HIPCHK(c, hipMemsetAsync(c->w<unsigned long long>(c->L.Xq) + (size_t)(c->turn & 1) * c->M * nbx,
+                                 0, (size_t)c->M * nbx * sizeof(unsigned long long), s));
     const Engine e = single_engine(c);
     HIPCHK(c, enqueue_push(e, false, 1, s));
     HIPCHK(c, enqueue_prep(e, 1, s));
@@ -796,6 +874,7 @@ void release_binding(mbt_ctx *c)
         (void)hipStreamSynchronize(c->stream_h);
     ring_free(c->mom);
     ring_free(c->prof);
+    ring_free(c->tmom);
     if (c->mirror && c->mirror != &c->plain_mirror)
         (void)hipHostFree(c->mirror);
     c->mirror = nullptr;
@@ -1056,6 +1135,71 @@ int mbt_set_resistive_wall(mbt_ctx *c, const mbt_resistive_wall *rw)
     });
 }
 
+int mbt_set_transverse(mbt_ctx *c, const mbt_transverse *tr)
+{
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "the transverse plane must be set before mbt_bind");
+        if (!tr) {
+            c->tr_on = false;
+            return MBT_OK;
+        }
+        if (!std::isfinite(tr->tune) || !std::isfinite(tr->chromaticity) || !std::isfinite(tr->alpha) ||
+            !(tr->beta_m > 0.0) || !std::isfinite(tr->beta_m) || !std::isfinite(tr->disp_m) ||
+            !std::isfinite(tr->disp_prime) || !(tr->emittance_m >= 0.0) ||
+            !std::isfinite(tr->emittance_m) || !(tr->tau_damp_s > 0.0))
+            return fail(c, MBT_EINVAL, "transverse plane: need finite values, beta > 0, eps >= 0, "
+                        "tau_damp > 0");
+        if (c->wake_mode != kWakeFP64)
+            return fail(c, MBT_EINVAL, "the transverse plane needs the FP64 wake");
+        c->tr = *tr;
+        c->tr_on = true;
+        return MBT_OK;
+    });
+}
+
+int mbt_set_transverse_wake(mbt_ctx *c, int32_t nres, const mbt_resonator *res)
+{
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
+        if (nres < 0 || nres > MBT_MAX_SHORT_RANGE || (nres > 0 && !res))
+            return fail(c, MBT_EINVAL, "need 0 <= nres <= %d", MBT_MAX_SHORT_RANGE);
+        for (int i = 0; i < nres; ++i)
+            if (!res_valid(res[i]))
+                return fail(c, MBT_EINVAL, "resonator %d: need Rs >= 0, Q > 0.5, fr > 0", i);
+        std::vector<Resonator> tw;
+        for (int i = 0; i < nres; ++i)
+            tw.push_back({res[i].rs_ohm, res[i].q, res[i].fr_Hz});
+        c->tw.swap(tw);
+        return MBT_OK;
+    });
+}
+
+int mbt_set_transverse_rw(mbt_ctx *c, const mbt_transverse_rw *rw)
+{
+    return guarded(c, [&]() -> int {
+        if (!c)
+            return MBT_EINVAL;
+        if (c->bound)
+            return fail(c, MBT_ESTATE, "wakes must be set before mbt_bind");
+        if (rw && !(std::isfinite(rw->radius_m) && rw->radius_m > 0.0 &&
+                    std::isfinite(rw->conductivity_S_m) && rw->conductivity_S_m > 0.0 &&
+                    std::isfinite(rw->length_m) && rw->length_m > 0.0 && rw->turns >= 1 &&
+                    rw->turns <= 1024))
+            return fail(c, MBT_EINVAL, "resistive wall: need radius, conductivity, length > 0 and "
+                        "1 <= turns <= 1024");
+        c->trw_on = rw != nullptr;
+        if (rw)
+            c->trw = *rw;
+        return MBT_OK;
+    });
+}
+
 int mbt_query_bytes(const mbt_ctx *c, int64_t N, size_t *state_bytes, size_t *work_bytes)
 {
     return guarded(static_cast<mbt_ctx *>(nullptr), [&]() -> int {
@@ -1065,7 +1209,7 @@ int mbt_query_bytes(const mbt_ctx *c, int64_t N, size_t *state_bytes, size_t *wo
             return MBT_ESTATE;
         if (N < 1 || N > ((int64_t)1 << 32))
             return MBT_EINVAL;
-        Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
+        Layout L = c->layout(N);
         *state_bytes = L.state_bytes;
         *work_bytes = L.total;
         return MBT_OK;
@@ -1091,7 +1235,7 @@ int bind_job(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
             return fail(c, MBT_EINVAL, "N must be in [1, 2^32]");
         if (!d_state || ((uintptr_t)d_state & 255) || (!st && (!d_work || ((uintptr_t)d_work & 255))))
             return fail(c, MBT_EINVAL, "device buffers must be non-null and 256-byte aligned");
-        Layout L = make_layout(c->M, N, c->nbins(), c->nlr());
+        Layout L = c->layout(N);
         if (st && L.total > (size_t)MBT_STATIC_WORK_BYTES)
             return fail(c, MBT_ENOSPC, "the job needs %zu workspace bytes; the static workspace "
                         "holds %zu", L.total, (size_t)MBT_STATIC_WORK_BYTES);
@@ -1110,6 +1254,8 @@ int bind_job(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
         c->N = N;
         c->tau = reinterpret_cast<double *>(d_state);
         c->delta = c->tau + (size_t)c->M * L.ld;
+        c->x = c->tr_on ? c->delta + (size_t)c->M * L.ld : nullptr;
+        c->xp = c->tr_on ? c->x + (size_t)c->M * L.ld : nullptr;
         c->work = work;
         c->stream_h = reinterpret_cast<hipStream_t>(hip_stream);
         c->device = device;
@@ -1221,6 +1367,31 @@ int bind_job(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
                                  hipMemcpyHostToDevice, c->stream_h));
         HIPCHK(c, hipMemcpyAsync(c->w<float>(L.Wf32), wf.data(), wf.size() * sizeof(float),
                                  hipMemcpyHostToDevice, c->stream_h));
+        if (c->tr_on) {
+            // transverse wake table on the grid (T[0] = 0), bunch buckets and
+            // charges for the wall
+            std::vector<double> T((size_t)nbx, 0.0), qb((size_t)M);
+            if (c->sr_on) {
+                const double dt = (c->grid.tau_max_s - c->grid.tau_min_s) / (double)nb;
+                for (const Resonator &r : c->tw) {
+                    const double wr = kTwoPi * r.fr, a = r.alpha(), wb = r.wbar();
+                    const double amp = r.rs * wr * wr / (r.q * wb);
+                    for (int k = 1; k < nb; ++k) {
+                        const double t = (double)k * dt;
+                        T[k] += amp * std::exp(-a * t) * std::sin(wb * t);
+                    }
+                }
+            }
+            for (int b = 0; b < M; ++b)
+                qb[b] = c->current[b] * c->T0;
+            HIPCHK(c, hipMemcpyAsync(c->w<double>(L.Tt), T.data(), T.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, c->stream_h));
+            HIPCHK(c, hipMemcpyAsync(c->w<int32_t>(L.bucket), c->bucket.data(), (size_t)M * sizeof(int32_t),
+                                     hipMemcpyHostToDevice, c->stream_h));
+            HIPCHK(c, hipMemcpyAsync(c->w<double>(L.qb), qb.data(), qb.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, c->stream_h));
+            HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        }
         HIPCHK(c, hipMemsetAsync(d_state, 0, L.state_bytes, c->stream_h));
         HIPCHK(c, hipStreamSynchronize(c->stream_h));
         if (st)
@@ -1232,6 +1403,9 @@ int bind_job(mbt_ctx *c, int64_t N, void *d_state, size_t state_bytes, void *d_w
         if (!rc)
             rc = ring_alloc(c, c->prof, c->w<uint32_t>(L.prof), (size_t)M * nbx * sizeof(uint32_t),
                             L.prof_slots, !st);
+        if (!rc && c->tr_on)
+            rc = ring_alloc(c, c->tmom, c->w<double>(L.tmom), (size_t)M * sizeof(mbt_tmoments),
+                            L.mom_slots, !st);
         if (rc) {
             release_binding(c);
             return rc;
@@ -1281,6 +1455,13 @@ int mbt_init_gaussian(mbt_ctx *c, double sigma_tau_s, double sigma_delta, uint64
                                     (uint32_t)seed, (uint32_t)(seed >> 32), c->stream_h));
         HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.phasor), 0,
                                  (size_t)std::max(c->nlr(), 1) * 2 * sizeof(double), c->stream_h));
+        if (c->tr_on) {
+            // a fresh start: the plane at rest until mbt_init_transverse, no wall history
+            HIPCHK(c, hipMemsetAsync(c->x, 0, (size_t)2 * c->M * c->L.ld * sizeof(double), c->stream_h));
+            if (c->rw_turns() > 0)
+                HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.H), 0,
+                                         (size_t)c->rw_turns() * c->M * sizeof(double), c->stream_h));
+        }
         c->seed = seed;
         c->turn = 0;
         c->have_particles = true;
@@ -1328,9 +1509,14 @@ int mbt_get_particles(mbt_ctx *c, int32_t bunch, double *tau, double *delta, int
     });
 }
 
-int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, int32_t stride)
+}  // extern "C"
+
+namespace {
+
+int track_job(mbt_ctx *c, int64_t nturns, mbt_moments *out, mbt_tmoments *tout, uint32_t *counts,
+              int32_t stride)
 {
-    return guarded(c, [&]() -> int {
+    {
         int rc = need_bound(c);
         if (rc)
             return rc;
@@ -1340,6 +1526,8 @@ int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, in
             return fail(c, MBT_EINVAL, "need nturns < 2^31 and the turn counter below 2^32");
         if (counts && (!c->sr_on || stride < 1))
             return fail(c, MBT_EINVAL, "profiles need a grid and stride >= 1");
+        if (tout && !c->tr_on)
+            return fail(c, MBT_EINVAL, "transverse moments need the transverse plane");
         if (nturns == 0)
             return MBT_OK;
         hipStream_t s = c->stream_h;
@@ -1348,19 +1536,23 @@ int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, in
             return rc;
         ring_start(c->mom, out);
         ring_start(c->prof, counts);
+        ring_start(c->tmom, tout);
         const Engine e = single_engine(c);
         for (int64_t t = 0; t < nturns; ++t) {
             const bool timed = c->timer.every > 0 && (t % c->timer.every) == 0;
             HIPCHK(c, ring_advance(c->mom, 1, s));
             HIPCHK(c, ring_advance(c->prof, profile_rows(t, 1, stride), s));
+            HIPCHK(c, ring_advance(c->tmom, 1, s));
             HIPCHK(c, enqueue_turn(e, (int)(t & 1), s, timed ? &c->timer : nullptr));
         }
         c->turn += nturns;
         HIPCHK(c, ring_flush(c->mom, s));
         HIPCHK(c, ring_flush(c->prof, s));
+        HIPCHK(c, ring_flush(c->tmom, s));
         HIPCHK(c, hipStreamSynchronize(s));
         HIPCHK(c, ring_land(c->mom));
         HIPCHK(c, ring_land(c->prof));
+        HIPCHK(c, ring_land(c->tmom));
         HIPCHK(c, timer_collect(c->timer));
         uint32_t status = 0;
         HIPCHK(c, hipMemcpy(&status, c->w<uint32_t>(c->L.status), sizeof status, hipMemcpyDeviceToHost));
@@ -1369,6 +1561,121 @@ int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, in
             return fail(c, MBT_ENUMERIC, "non-finite bunch moment during turns %lld..%lld",
                         (long long)(c->turn - nturns), (long long)(c->turn - 1));
         }
+        return MBT_OK;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbt_track(mbt_ctx *c, int64_t nturns, mbt_moments *out, uint32_t *counts, int32_t stride)
+{
+    return guarded(c, [&]() -> int { return track_job(c, nturns, out, nullptr, counts, stride); });
+}
+
+int mbt_track2(mbt_ctx *c, int64_t nturns, mbt_moments *out, mbt_tmoments *tout, uint32_t *counts,
+               int32_t stride)
+{
+    return guarded(c, [&]() -> int { return track_job(c, nturns, out, tout, counts, stride); });
+}
+
+int mbt_init_transverse(mbt_ctx *c, double emittance_m, double offset_m)
+{
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!c->tr_on)
+            return fail(c, MBT_ESTATE, "no transverse plane");
+        if (!(emittance_m >= 0.0) || !std::isfinite(emittance_m) || !std::isfinite(offset_m))
+            return fail(c, MBT_EINVAL, "emittance must be finite and >= 0, offset finite");
+        const double sx = std::sqrt(emittance_m * c->tr.beta_m);
+        const double sxp = std::sqrt(emittance_m / c->tr.beta_m);
+        HIPCHK(c, launch_init_transverse(c->x, c->xp, c->L.ld, c->N, c->M, c->w<uint32_t>(c->L.stream),
+                                         sx, sxp, c->tr.alpha, offset_m, (uint32_t)c->seed,
+                                         (uint32_t)(c->seed >> 32), c->stream_h));
+        if (c->rw_turns() > 0)
+            HIPCHK(c, hipMemsetAsync(c->w<double>(c->L.H), 0,
+                                     (size_t)c->rw_turns() * c->M * sizeof(double), c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        c->dirty = true;
+        return MBT_OK;
+    });
+}
+
+int mbt_set_transverse_particles(mbt_ctx *c, int32_t bunch, const double *x, const double *xp,
+                                 int32_t where)
+{
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!c->tr_on)
+            return fail(c, MBT_ESTATE, "no transverse plane");
+        if (bunch < 0 || bunch >= c->M || !x || !xp || (where != MBT_HOST && where != MBT_DEVICE))
+            return fail(c, MBT_EINVAL, "bad bunch index, null array or location");
+        const size_t bytes = (size_t)c->N * sizeof(double);
+        const hipMemcpyKind kind = where == MBT_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        HIPCHK(c, hipMemcpyAsync(c->x + (size_t)bunch * c->L.ld, x, bytes, kind, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(c->xp + (size_t)bunch * c->L.ld, xp, bytes, kind, c->stream_h));
+        if (where == MBT_HOST)
+            HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        c->dirty = true;
+        return MBT_OK;
+    });
+}
+
+int mbt_get_transverse_particles(mbt_ctx *c, int32_t bunch, double *x, double *xp, int32_t where)
+{
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (!c->tr_on)
+            return fail(c, MBT_ESTATE, "no transverse plane");
+        if (bunch < 0 || bunch >= c->M || !x || !xp || (where != MBT_HOST && where != MBT_DEVICE))
+            return fail(c, MBT_EINVAL, "bad bunch index, null array or location");
+        const size_t bytes = (size_t)c->N * sizeof(double);
+        const hipMemcpyKind kind = where == MBT_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        HIPCHK(c, hipMemcpyAsync(x, c->x + (size_t)bunch * c->L.ld, bytes, kind, c->stream_h));
+        HIPCHK(c, hipMemcpyAsync(xp, c->xp + (size_t)bunch * c->L.ld, bytes, kind, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        return MBT_OK;
+    });
+}
+
+int mbt_get_rw_history(mbt_ctx *c, double *H)
+{
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (c->rw_turns() == 0)
+            return fail(c, MBT_ESTATE, "no long-range resistive wall");
+        if (!H)
+            return fail(c, MBT_EINVAL, "null array");
+        HIPCHK(c, hipMemcpyAsync(H, c->w<double>(c->L.H), (size_t)c->rw_turns() * c->M * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        return MBT_OK;
+    });
+}
+
+int mbt_set_rw_history(mbt_ctx *c, const double *H)
+{
+    return guarded(c, [&]() -> int {
+        int rc = need_bound(c);
+        if (rc)
+            return rc;
+        if (c->rw_turns() == 0)
+            return fail(c, MBT_ESTATE, "no long-range resistive wall");
+        if (!H)
+            return fail(c, MBT_EINVAL, "null array");
+        HIPCHK(c, hipMemcpyAsync(c->w<double>(c->L.H), H, (size_t)c->rw_turns() * c->M * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream_h));
+        HIPCHK(c, hipStreamSynchronize(c->stream_h));
+        c->dirty = true;  // the wall kick of the next turn comes from the new history
         return MBT_OK;
     });
 }
@@ -1508,6 +1815,8 @@ int mbt_set_wake_precision(mbt_ctx *c, int32_t mode)
             return MBT_EINVAL;
         if (mode < MBT_WAKE_FP64 || mode > MBT_WAKE_BF16X3)
             return fail(c, MBT_EINVAL, "unknown wake precision %d", mode);
+        if (c->tr_on && mode != MBT_WAKE_FP64)
+            return fail(c, MBT_EINVAL, "a job with the transverse plane keeps the FP64 wake");
         if (mode != c->wake_mode)
             c->dirty = true;  // the stored wake potential used the other arithmetic
         c->wake_mode = mode;
@@ -1842,6 +2151,8 @@ int mbt_batch_query_bytes(mbt_ctx *const *jobs, int32_t njobs, size_t *work_byte
                 return MBT_ESTATE;
             if (jobs[j]->static_ws)
                 return MBT_EINVAL;  // the static workspace is not a batch job's own
+            if (jobs[j]->tr_on)
+                return MBT_EINVAL;  // transverse jobs are tracked alone
         }
         size_t a, b, w;
         *work_bytes = batch_layout(jobs, njobs, &a, &b, &w);

@@ -16,7 +16,10 @@ constexpr int kMaxLR = 4;            // long-range resonators
 #endif
 constexpr int kPushThreads = MBT_PUSH_THREADS;         // wavefronts of 64
 constexpr int kPairsPerThread = MBT_PAIRS_PER_THREAD;  // most particle pairs per thread per tile
-constexpr int kPartStride = 4 + 2 * kMaxLR;  // doubles per tile partial
+constexpr int kPartTr = 4 + 2 * kMaxLR;      // first transverse slot of a tile partial
+constexpr int kPartStride = kPartTr + 4;     // doubles per tile partial:
+                                             // tau, tau^2, delta, delta^2, deposits,
+                                             // x, x^2, x', x'^2
 constexpr int kPrepThreads = 256;
 constexpr int kConvOutMax = 64;      // wake-potential bins per prep workgroup, at most
 constexpr int kConvOutMin = 16;      // ... and at least
@@ -45,6 +48,25 @@ struct MapConst {
     double lr_alpha[kMaxLR];  // omega_r / 2Q
     double lr_wbar[kMaxLR];   // sqrt(omega_r^2 - alpha^2)
 };
+
+// Constants of the transverse plane (Sec. 2.2 Eqs. 3-5, Sec. 2.3).
+struct TransConst {
+    double qfrac;         // frac(Q)
+    double chrom;         // Q'
+    double alpha, beta, gamma;
+    double disp, disp_p;  // D, D'
+    double noise_x;       // sqrt(eps beta D_x)
+    double noise_xp;      // sqrt(eps gamma D_x)
+    int noise_on;
+    int rw_turns;         // K of the long-range wall (0: off)
+    double rw_amp;        // L / (pi b^3) [1/m^2]
+    double rw_arg;        // Z0 c / (pi sigma) [s]: W_T(t) = rw_amp sqrt(rw_arg / t)
+    double T0, T_rf;
+};
+
+// Fixed-point scale of the dipole sums: x is summed as round(x 2^52) in int64.
+constexpr double kDipoleScale = 4503599627370496.0;  // 2^52
+constexpr double kDipoleUnit = 1.0 / kDipoleScale;
 
 // Everything a kernel needs about one job, resident in device memory.  The
 // turn counter lives on the device in two slots, so a captured run of turns
@@ -90,6 +112,19 @@ struct JobDesc {
     uint32_t *status;         // bit 0: non-finite moment
     uint32_t *clock;          // [2] turn counter by launch phase (see below)
     int conv_out;             // wake-potential bins per prep workgroup (16, 32 or 64)
+    // transverse plane (tr_on = 0: none of the fields below is used)
+    int tr_on;
+    TransConst t;
+    double *x;                // [M][ld]
+    double *xp;               // [M][ld]
+    const double *Tt;         // [nbins] transverse wake table
+    double *U;                // [M][nbins] transverse kick per bin [rad]
+    unsigned long long *Xq;   // [2][M][nbins] dipole sums (int64, units 2^-52 m) by turn parity
+    double *tmom_ring;        // [mom_slots][M][4]
+    double *H;                // [rw_turns][M] bunch centroids <x> by turn mod K
+    double *rwk;              // [M] wall kick for the next turn [rad]
+    const int32_t *bucket;    // [M] bucket of each bunch
+    const double *qb;         // [M] bunch charge I_b T0 [C]
 };
 
 // One unit of work: a tile (push) or a wake-potential chunk (prep) of a bunch.
@@ -138,6 +173,7 @@ struct PrepLaunch {
     // descriptor, nor the descriptor before the counter.  inner = 0: tables.
     int inner;
     const uint32_t *clk;
+    int tr;                   // the job has the transverse plane (one job per launch)
 };
 struct WakeLaunch {
     int phase;
@@ -149,6 +185,12 @@ struct WakeLaunch {
     int inner;                // as in PrepLaunch
     const uint32_t *clk;
 };
+struct RwLaunch {
+    int phase;
+    const JobDesc *job;       // one job
+    int M;
+    const uint32_t *clk;      // its turn counter
+};
 struct ScanLaunch {
     const JobDesc *jobs;
     int njobs;
@@ -156,6 +198,12 @@ struct ScanLaunch {
 };
 
 hipError_t launch_push(const PushLaunch &l, bool push, hipStream_t s);
+hipError_t launch_push_tr(const PushLaunch &l, bool push, hipStream_t s);
+hipError_t launch_rw(const RwLaunch &l, hipStream_t s);
+hipError_t launch_init_transverse(double *x, double *xp, int64_t ld, int64_t N, int M,
+                                  const uint32_t *stream, double sx, double sxp, double alpha,
+                                  double offset, uint32_t key0, uint32_t key1, hipStream_t s);
+size_t push_tr_lds_bytes(int nbins, int nsub);
 hipError_t launch_prep(const PrepLaunch &l, hipStream_t s);
 hipError_t launch_scan(const ScanLaunch &l, hipStream_t s);
 hipError_t launch_wake(const WakeLaunch &l, hipStream_t s);

@@ -206,10 +206,10 @@ __device__ __forceinline__ bool noise_on(const MapConst &c)
 //   wake: vb = the bin's V/E0 (staged in LDS already divided by E0; read
 //         before the noise so that the LDS latency hides behind it)
 //   long range: Re[(V~/E0) exp((-alpha + i wbar) tau)]
-template <int NLR, int MAP>
-__device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
-                                           const double (&seen)[NLR > 0 ? NLR : 1][2], double sx,
-                                           double cx, double z, double &t, double &d)
+// Energy gain in the main and harmonic cavities over E0, from sin and cos of
+// w_rf tau.
+template <int MAP>
+__device__ __forceinline__ double rf_energy(const MapConst &c, double sx, double cx)
 {
     double k = fma(c.rf_a, cx, -c.rf_b * sx);
     if (hc_on<MAP>(c)) {
@@ -217,6 +217,36 @@ __device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
         multiple_angle(MAP == kMapWakeNoiseHC3 ? 3 : c.hc_n, sx, cx, sn, cn);
         k += fma(c.hc_a, cn, -c.hc_b * sn);
     }
+    return k;
+}
+
+// The rest of the kick after the cavities' gain erf, then damping, noise
+// and drift.
+template <int NLR>
+__device__ __forceinline__ void kick_rest(const MapConst &c, double k, const double vb,
+                                          const double (&seen)[NLR > 0 ? NLR : 1][2], double z,
+                                          double &t, double &d)
+{
+    k -= c.u0_e;
+    k -= vb;  // the bin's wake voltage: 0 outside the grid or without a wake
+#pragma unroll
+    for (int r = 0; r < NLR; ++r) {
+        const double e = exp_wave(-c.lr_alpha[r] * t);
+        double s, co;
+        sincos_wave(c.lr_wbar[r] * t, s, co);
+        k -= e * fma(seen[r][0], co, -seen[r][1] * s);
+    }
+    const double dn = fma(c.noise, z, (d + k) * c.one_minus_D);
+    d = dn;
+    t = fma(c.drift, dn, t);
+}
+
+template <int NLR, int MAP>
+__device__ __forceinline__ void kick_drift(const MapConst &c, const double vb,
+                                           const double (&seen)[NLR > 0 ? NLR : 1][2], double sx,
+                                           double cx, double z, double &t, double &d)
+{
+    double k = rf_energy<MAP>(c, sx, cx);
     k -= c.u0_e;
     k -= vb;  // the bin's wake voltage: 0 outside the grid or without a wake
 #pragma unroll
@@ -1062,6 +1092,414 @@ __global__ __launch_bounds__(kPrepThreads) void k_scan(const ScanLaunch L)
 }
 
 // ---------------------------------------------------------------------------
+// Transverse plane (Sec. 2.2 Eqs. 3-5; Sec. 2.3, Eq. 6 second line and the
+// long-range resistive wall of its last paragraph).  k_push_tr is k_push with
+// one transverse plane (x, x') moved beside (tau, delta): the same
+// longitudinal arithmetic, plus per particle the wall kick of its bunch and
+// the transverse wake kick of its bin on x', the betatron rotation about the
+// dispersive orbit, adiabatic damping and the plane's noise; its epilogue
+// adds the bins' dipole sums (exact integer sums in LDS, merged into the
+// bunch's buffer with 64-bit integer atomics) and the sums of x, x^2, x',
+// x'^2.  Every switch is read from the descriptor (no compile-time map).
+// ---------------------------------------------------------------------------
+
+// x rounded to the nearest multiple of 2^-52 m, as that integer (|x| < 2^11 m):
+// the scaling is exact, rint rounds once, and the integral double is split
+// into 32-bit halves exactly.
+__device__ __forceinline__ unsigned long long dipole_q(double x)
+{
+    const double r = rint(x * kDipoleScale);
+    const double hi = floor(r * 0x1.0p-32);
+    const double lo = fma(hi, -4294967296.0, r);  // r - hi 2^32, in [0, 2^32), exact
+    return ((unsigned long long)(long long)(int)hi << 32) + (unsigned long long)(uint32_t)lo;
+}
+
+// Transverse part of one particle's turn (the longitudinal state d is the
+// value before the kick; erf the cavities' energy gain over E0).
+__device__ __forceinline__ void betatron(const TransConst &tc, double din, double erf, double ub,
+                                         double rwk, bool rw, double zx, double zxp, double &x,
+                                         double &xp)
+{
+    double p = xp;
+    if (rw)
+        p = p + rwk;  // the wall's kick of the previous turn's passages
+    p = p + ub;       // the bin's transverse wake kick (0 outside the grid)
+    const double psi = 6.283185307179586 * (tc.qfrac + tc.chrom * din);
+    double sn, cs;
+    sincos_cw(psi, sn, cs);
+    const double xb = x - tc.disp * din;
+    const double xpb = p - tc.disp_p * din;
+    double x2 = (tc.disp * din + (cs + tc.alpha * sn) * xb) + (tc.beta * sn) * xpb;
+    double xp2 = (tc.disp_p * din - (tc.gamma * sn) * xb) + (cs - tc.alpha * sn) * xpb;
+    xp2 = xp2 * ((1.0 + din) / ((1.0 + din) + erf));
+    if (tc.noise_on) {
+        x2 = x2 + tc.noise_x * zx;
+        xp2 = xp2 + tc.noise_xp * zxp;
+    }
+    x = x2;
+    xp = xp2;
+}
+
+template <int NLR, bool PUSH>
+__global__ __launch_bounds__(kPushThreads, 2) void k_push_tr(
+    const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
+    const int grid, const int phase)
+{
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int NP = 4 + 2 * NLR;
+    constexpr int NA = NP + 4;  // + x, x^2, x', x'^2
+
+    for (int it = blockIdx.x; it < nitems; it += grid) {
+        const Item item = items[it];
+        const JobDesc &J = jobs[item.job];
+        const MapConst &c = J.c;
+        const TransConst &tc = J.t;
+        const int nb = c.nbins, nbx = nb > 0 ? nb : 1;
+        const int b = item.bunch;
+        const uint32_t tile = item.part;
+        const uint32_t clock = __builtin_amdgcn_readfirstlane(J.clock[phase]);
+        const uint32_t turn = clock;
+
+        // LDS: V/E0 and U of every bin plus a zero slot, the dipole sums
+        // (bins plus an outside slot), the sub-histograms, the wave sums
+        double *Vs = smem;                        // [nb + 1]
+        double *Us = Vs + nb + 1;                 // [nb + 1]
+        unsigned long long *xh =
+            reinterpret_cast<unsigned long long *>(Us + nb + 1);  // [nb + 1]
+        uint32_t *hist = reinterpret_cast<uint32_t *>(xh + nb + 1);
+        const int nbh = nb + 1;
+        double *red = reinterpret_cast<double *>(xh + nb + 1) + ((J.nsub * nbh + 1) >> 1);
+
+        for (int k = tid; k < J.nsub * nbh; k += kPushThreads)
+            hist[k] = 0u;
+        for (int k = tid; k <= nb; k += kPushThreads) {
+            xh[k] = 0ull;
+            if (PUSH && c.sr_on) {
+                Vs[k] = k < nb ? J.V[(size_t)b * nb + k] * c.inv_E0 : 0.0;
+                Us[k] = k < nb ? J.U[(size_t)b * nb + k] : 0.0;
+            }
+        }
+        __syncthreads();
+        uint32_t *hist_w = hist + (J.nsub > 0 ? (wave % J.nsub) * nbh : 0);
+
+        double seen[NLR > 0 ? NLR : 1][2];
+#pragma unroll
+        for (int r = 0; r < NLR; ++r) {
+            seen[r][0] = J.seen[((size_t)r * J.M + b) * 2 + 0] * c.inv_E0;
+            seen[r][1] = J.seen[((size_t)r * J.M + b) * 2 + 1] * c.inv_E0;
+        }
+        const bool rw = tc.rw_turns > 0;
+        const double rwk = rw ? J.rwk[b] : 0.0;
+        const uint32_t stream = J.stream[b];
+        const size_t row = (size_t)b * J.ld;
+        double acc[NA];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            acc[i] = 0.0;
+
+        const int ppt = J.ppt;
+        const uint32_t pair0 = tile * (uint32_t)(kPushThreads * ppt);
+        const uint32_t n_last = (uint32_t)(J.N - 1);
+#pragma unroll 1
+        for (int s = 0; s < ppt; ++s) {
+            const uint32_t p = pair0 + (uint32_t)(s * kPushThreads + tid);
+            const uint32_t j0 = 2u * p;
+            if (j0 > n_last)
+                break;
+            const bool two = j0 < n_last;
+            double t[2], d[2], x[2], xp[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const uint32_t j = i == 0 || two ? j0 + i : j0;
+                t[i] = J.tau[row + j];
+                d[i] = J.delta[row + j];
+                x[i] = J.x[row + j];
+                xp[i] = J.xp[row + j];
+            }
+            if (PUSH) {
+                double vb[2] = {0.0, 0.0}, ub[2] = {0.0, 0.0};
+                if (c.sr_on) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        const int k = bin_of(c, t[i]);
+                        vb[i] = Vs[k >= 0 ? k : nb];
+                        ub[i] = Us[k >= 0 ? k : nb];
+                    }
+                }
+                double z[2] = {0.0, 0.0}, zx[2] = {0.0, 0.0}, zxp[2] = {0.0, 0.0};
+                if (c.noise_on)
+                    normal_pair(p, stream, turn, 0u, J.key0, J.key1, z[0], z[1]);
+                if (tc.noise_on) {
+                    normal_pair(p, stream, turn, 2u, J.key0, J.key1, zx[0], zx[1]);
+                    normal_pair(p, stream, turn, 3u, J.key0, J.key1, zxp[0], zxp[1]);
+                }
+                double sx[2], cx[2];
+                rf_phase(c.w_rf * t[0], c.w_rf * t[1], sx[0], cx[0], sx[1], cx[1]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const double erf = rf_energy<kMapGeneric>(c, sx[i], cx[i]);
+                    betatron(tc, d[i], erf, ub[i], rwk, rw, zx[i], zxp[i], x[i], xp[i]);
+                    kick_rest<NLR>(c, erf, vb[i], seen, z[i], t[i], d[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                if (i == 1 && !two)
+                    break;
+                if (c.sr_on) {
+                    const int k = bin_of(c, t[i]);
+                    atomicAdd(&hist_w[k >= 0 ? k : nb], 1u);
+                    atomicAdd(&xh[k >= 0 ? k : nb], dipole_q(x[i]));
+                }
+                acc[0] += t[i];
+                acc[1] = fma(t[i], t[i], acc[1]);
+                acc[2] += d[i];
+                acc[3] = fma(d[i], d[i], acc[3]);
+#pragma unroll
+                for (int r = 0; r < NLR; ++r) {
+                    const double e = exp_wave(c.lr_alpha[r] * t[i]);
+                    double sn, co;
+                    sincos_wave(c.lr_wbar[r] * t[i], sn, co);
+                    acc[4 + 2 * r] = fma(e, co, acc[4 + 2 * r]);
+                    acc[5 + 2 * r] = fma(-e, sn, acc[5 + 2 * r]);
+                }
+                acc[NP + 0] += x[i];
+                acc[NP + 1] = fma(x[i], x[i], acc[NP + 1]);
+                acc[NP + 2] += xp[i];
+                acc[NP + 3] = fma(xp[i], xp[i], acc[NP + 3]);
+            }
+            if (PUSH) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    if (i == 1 && !two)
+                        break;
+                    J.tau[row + j0 + i] = t[i];
+                    J.delta[row + j0 + i] = d[i];
+                    J.x[row + j0 + i] = x[i];
+                    J.xp[row + j0 + i] = xp[i];
+                }
+            }
+        }
+
+        // Fixed-order tile reduction, as in k_push; the transverse sums go to
+        // the partial's transverse slots.
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const double v = wave_sum(acc[i]);
+            if (lane == 0)
+                red[wave * kPartStride + i] = v;
+        }
+        __syncthreads();
+        if (tid < NA) {
+            double sum = red[tid];
+            for (int w = 1; w < kPushThreads / 64; ++w)
+                sum += red[w * kPartStride + tid];
+            const int slot = tid < NP ? tid : kPartTr + (tid - NP);
+            J.partials[((size_t)b * J.ntiles + tile) * kPartStride + slot] = sum;
+        }
+        if (c.sr_on) {
+            const size_t off = ((size_t)((clock + 1u) & 1u) * J.M + b) * nbx;
+            uint32_t *out = J.counts + off;
+            unsigned long long *xout = J.Xq + off;
+            for (int k = tid; k < nb; k += kPushThreads) {
+                uint32_t sum = 0;
+                for (int q = 0; q < J.nsub; ++q)
+                    sum += hist[q * nbh + k];
+                if (sum) {
+                    atomicAdd(&out[k], sum);
+                    atomicAdd(&xout[k], xh[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+size_t push_tr_lds_bytes(int nbins, int nsub)
+{
+    size_t v = (size_t)3 * (nbins + 1) * sizeof(double);  // V, U, dipole sums
+    size_t h = (size_t)nsub * (size_t)(nbins + 1) * sizeof(uint32_t);
+    h = (h + 7) & ~(size_t)7;
+    return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
+}
+
+// Transverse moments of bunch b (Sec. 2.4) into the ring, and its centroid
+// into the wall's history, from the transverse slots of the tile partials;
+// the same fixed order as finish_sums.
+__device__ void finish_sums_tr(const JobDesc &J, int b, uint32_t clock)
+{
+    __shared__ double tred[kPrepThreads / 64][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = tid; t < J.ntiles; t += kPrepThreads) {
+        const double *p = J.partials + ((size_t)b * J.ntiles + t) * kPartStride + kPartTr;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            s[i] += p[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double v = wave_sum(s[i]);
+        if (lane == 0)
+            tred[wave][i] = v;
+    }
+    __syncthreads();
+    const int32_t rel = (int32_t)(clock - J.base);
+    if (tid == 0) {
+        double tot[4];
+        for (int i = 0; i < 4; ++i) {
+            tot[i] = tred[0][i];
+            for (int w = 1; w < kPrepThreads / 64; ++w)
+                tot[i] += tred[w][i];
+        }
+        const double invN = 1.0 / (double)J.N;
+        const double mx = tot[0] * invN, mp = tot[2] * invN;
+        const double vx = tot[1] * invN - mx * mx, vp = tot[3] * invN - mp * mp;
+        if (rel >= 0) {
+            double *m = J.tmom_ring + ((size_t)(rel & (J.mom_slots - 1)) * J.M + b) * 4;
+            m[0] = mx;
+            m[1] = mp;
+            m[2] = sqrt(vx > 0.0 ? vx : 0.0);
+            m[3] = sqrt(vp > 0.0 ? vp : 0.0);
+            if (J.t.rw_turns > 0)
+                J.H[(size_t)(clock % (uint32_t)J.t.rw_turns) * J.M + b] = mx;
+        }
+        if (!isfinite(mx) || !isfinite(mp) || !isfinite(vx) || !isfinite(vp))
+            atomicOr(J.status, 1u);
+    }
+    __syncthreads();
+}
+
+// Bins [k0, k1) of bunch b's transverse kick (Sec. 2.3, Eq. 6 second line):
+// U[k] = (qpp / E0) sum_{m<k} T[k-m] X[m], X from the exact dipole sums.  The
+// same chunking and fixed-order combination as conv_chunk (T[0] = 0, so the
+// sum may run to m = k); clears the dipole buffer the next push fills.
+__device__ void conv_chunk_tr(const JobDesc &J, int b, int chunk, uint32_t clock, double *psm)
+{
+    __shared__ int t_lo;
+    const int w = J.conv_out, K = kPrepThreads / w;
+    const int tid = threadIdx.x;
+    const int nb = J.c.nbins;
+    const int k0 = chunk * w, k1 = min(k0 + w, nb);
+    const unsigned long long *xin = J.Xq + ((size_t)((clock + 1u) & 1u) * J.M + b) * nb;
+    unsigned long long *xclr = J.Xq + ((size_t)(clock & 1u) * J.M + b) * nb;
+    double *sT = psm;
+    double *sX = psm + nb;
+    __syncthreads();  // the LDS may still be read by the longitudinal chunk
+    if (tid == 0)
+        t_lo = k1;
+    __syncthreads();
+    int lo = k1;
+    for (int k = tid; k < k1; k += kPrepThreads) {
+        const long long q = (long long)xin[k];
+        sT[k] = J.Tt[k];
+        sX[k] = (double)q * kDipoleUnit;
+        if (q != 0 && k < lo)
+            lo = k;
+    }
+    if (lo < k1)
+        atomicMin(&t_lo, lo);
+    __syncthreads();
+    lo = t_lo;
+    const int o = tid / K, q = tid % K;
+    const int k = k0 + o;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (k < k1) {
+        int m = lo + q;
+        for (; m + K <= k; m += 2 * K) {
+            acc0 = fma(sT[k - m], sX[m], acc0);
+            acc1 = fma(sT[k - m - K], sX[m + K], acc1);
+        }
+        if (m <= k)
+            acc0 = fma(sT[k - m], sX[m], acc0);
+    }
+    double v = acc0 + acc1;
+    for (int off = K >> 1; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    if (q == 0 && k < k1)
+        J.U[(size_t)b * nb + k] = (J.qpp[b] * J.c.inv_E0) * v;
+    for (int kk = k0 + tid; kk < k1; kk += kPrepThreads)
+        xclr[kk] = 0ull;
+}
+
+// The between-turn work of a job with the transverse plane: the prep's
+// longitudinal work, then its transverse counterpart.
+template <int NLR>
+__global__ __launch_bounds__(kPrepThreads) void k_prep_tr(const PrepLaunch L)
+{
+    extern __shared__ double psm[];
+    const int bx = blockIdx.x;
+    const Item item = L.inner > 0 ? Item{0, (uint16_t)(bx / L.inner), (uint32_t)(bx % L.inner)}
+                                  : L.items[bx];
+    const JobDesc &J = L.jobs[item.job];
+    const uint32_t clock = L.clk ? L.clk[L.phase] : J.clock[L.phase];
+    prep_body<NLR>(L, item, J, clock, psm);
+    if (item.part == 0)
+        finish_sums_tr(J, item.bunch, clock);
+    if (J.c.sr_on)
+        conv_chunk_tr(J, item.bunch, (int)item.part, clock, psm);
+    if (item.bunch == 0 && item.part == 0 && threadIdx.x == 0)
+        J.clock[L.phase ^ 1] = clock + 1u;
+}
+
+// The long-range resistive wall (Sec. 2.3, last paragraph), after the prep
+// has recorded the centroids of turn n (the counter reads n): the kick that
+// bunch b's particles get at the start of turn n + 1, from the passages of
+// bunches b' < b in turn n and of every bunch in turns n - K + 1 .. n - 1,
+// each source a rigid dipole of charge I_b' T0 at its centroid.  One
+// workgroup per bunch; the K M terms are split over the threads and combined
+// in a fixed order.
+__global__ __launch_bounds__(256) void k_rw(const RwLaunch L)
+{
+    __shared__ double wred[4];
+    const JobDesc &J = *L.job;
+    const TransConst &tc = J.t;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const uint32_t clock = L.clk[L.phase];
+    // the turn whose passages receive the kick (-1 before the first turn)
+    const int64_t target = (int64_t)J.base + (int64_t)(int32_t)(clock - J.base);
+    const int K = tc.rw_turns, M = J.M;
+    const int64_t nterms = (int64_t)(K - 1) * M + b;
+    double acc = 0.0;
+    for (int64_t i = tid; i < nterms; i += 256) {
+        const int age = K - 1 - (int)(i / M);
+        const int bs = (int)(i % M);
+        const int64_t m = target - age;
+        if (m < 0)
+            continue;
+        const double dt = (double)age * tc.T0 + (double)(J.bucket[b] - J.bucket[bs]) * tc.T_rf;
+        const double wt = tc.rw_amp * sqrt(tc.rw_arg / dt);
+        acc += J.qb[bs] * J.H[(size_t)(m % K) * M + bs] * wt;
+    }
+    const double v = wave_sum(acc);
+    if ((tid & 63) == 0)
+        wred[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0)
+        J.rwk[b] = (((wred[0] + wred[1]) + wred[2]) + wred[3]) * J.c.inv_E0;
+}
+
+// Matched Gaussian (x, x'): one Box-Muller pair of the INIT stream, tag 4,
+// per particle.
+__global__ __launch_bounds__(256) void k_init_tr(double *x, double *xp, int64_t ld, int64_t N,
+                                                 const uint32_t *stream, double sx, double sxp,
+                                                 double alpha, double offset, uint32_t k0,
+                                                 uint32_t k1)
+{
+    const int b = blockIdx.y;
+    const uint32_t sb = stream[b];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double z0, z1;
+        normal_pair((uint32_t)j, sb, 0u, 4u, k0, k1, z0, z1);
+        x[(size_t)b * ld + j] = offset + sx * z0;
+        xp[(size_t)b * ld + j] = sxp * (z1 - alpha * z0);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Initial distribution and raw Philox.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_init_gauss(double *tau, double *delta, int64_t ld,
@@ -1153,6 +1591,53 @@ hipError_t launch_push(const PushLaunch &l, bool push, hipStream_t s)
     }
 }
 
+template <int NLR>
+static hipError_t push_tr_n(const PushLaunch &l, bool push, hipStream_t s)
+{
+    const size_t lds = push_tr_lds_bytes(l.nbins_max, l.nsub_max);
+    if (push)
+        hipLaunchKernelGGL((k_push_tr<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s,
+                           l.jobs, l.items, l.nitems, l.grid, l.phase);
+    else
+        hipLaunchKernelGGL((k_push_tr<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s,
+                           l.jobs, l.items, l.nitems, l.grid, l.phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_tr(const PushLaunch &l, bool push, hipStream_t s)
+{
+    if (l.nitems < 1 || l.grid < 1)
+        return hipErrorInvalidValue;
+    switch (l.nlr) {
+    case 0: return push_tr_n<0>(l, push, s);
+    case 1: return push_tr_n<1>(l, push, s);
+    case 2: return push_tr_n<2>(l, push, s);
+    case 3: return push_tr_n<3>(l, push, s);
+    case 4: return push_tr_n<4>(l, push, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rw(const RwLaunch &l, hipStream_t s)
+{
+    if (l.M < 1 || !l.job || !l.clk)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rw, dim3(l.M), dim3(256), 0, s, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_transverse(double *x, double *xp, int64_t ld, int64_t N, int M,
+                                  const uint32_t *stream, double sx, double sxp, double alpha,
+                                  double offset, uint32_t key0, uint32_t key1, hipStream_t s)
+{
+    int64_t bx = (N + 255) / 256;
+    if (bx > 4096)
+        bx = 4096;
+    hipLaunchKernelGGL(k_init_tr, dim3((unsigned)bx, M), dim3(256), 0, s, x, xp, ld, N, stream,
+                       sx, sxp, alpha, offset, key0, key1);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const PrepLaunch &l, hipStream_t s)
 {
     if (l.nitems < 1)
@@ -1160,6 +1645,17 @@ hipError_t launch_prep(const PrepLaunch &l, hipStream_t s)
     size_t lds = (size_t)2 * l.nbins_max * sizeof(double);
     if (lds == 0)
         lds = 16;
+    if (l.tr) {
+        switch (l.nlr_max) {
+        case 0: hipLaunchKernelGGL((k_prep_tr<0>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+        case 1: hipLaunchKernelGGL((k_prep_tr<1>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+        case 2: hipLaunchKernelGGL((k_prep_tr<2>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+        case 3: hipLaunchKernelGGL((k_prep_tr<3>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+        case 4: hipLaunchKernelGGL((k_prep_tr<4>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (l.nlr_max) {
     case 0: hipLaunchKernelGGL((k_prep<0>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;
     case 1: hipLaunchKernelGGL((k_prep<1>), dim3(l.nitems), dim3(kPrepThreads), lds, s, l); break;

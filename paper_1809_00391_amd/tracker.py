@@ -85,6 +85,8 @@ class Tracker:
         self.N = 0
         self.nbins = 0
         self.n_lr = 0
+        self.tr_on = False
+        self.rw_turns = 0
         self.state = None
         self.work = None
         self.stream = None
@@ -148,6 +150,78 @@ class Tracker:
         else:
             r = _abi.ResistiveWall(*map(float, rw))
             self._check(self._L.mbt_set_resistive_wall(self._h, C.byref(r)))
+
+    # ---- transverse plane ----------------------------------------------
+    def set_transverse(self, plane):
+        """One transverse plane (dict with tune, chromaticity, alpha, beta_m,
+        disp_m, disp_prime, emittance_m, tau_damp_s), or None."""
+        if plane is None:
+            self._check(self._L.mbt_set_transverse(self._h, None))
+            self.tr_on = False
+            return
+        t = _abi.Transverse(*[float(plane[k]) for k in (
+            "tune", "chromaticity", "alpha", "beta_m", "disp_m", "disp_prime", "emittance_m",
+            "tau_damp_s")])
+        self._check(self._L.mbt_set_transverse(self._h, C.byref(t)))
+        self.tr_on = True
+
+    def set_transverse_wake(self, resonators):
+        """Transverse short-range resonators (R_s in Ohm/m, Q, f_r)."""
+        arr, n = _resonators(resonators)
+        self._check(self._L.mbt_set_transverse_wake(self._h, n, arr))
+
+    def set_transverse_rw(self, rw):
+        """Long-range transverse resistive wall (radius m, conductivity S/m,
+        length m, turns), or None."""
+        self.rw_turns = 0 if rw is None else int(rw[3])
+        if rw is None:
+            self._check(self._L.mbt_set_transverse_rw(self._h, None))
+            return
+        r = _abi.TransverseRW(float(rw[0]), float(rw[1]), float(rw[2]), int(rw[3]))
+        self._check(self._L.mbt_set_transverse_rw(self._h, C.byref(r)))
+
+    def init_transverse(self, emittance, offset=0.0):
+        self._check(self._L.mbt_init_transverse(self._h, float(emittance), float(offset)))
+
+    def set_transverse_particles(self, bunch, x, xp):
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        b = np.ascontiguousarray(xp, dtype=np.float64)
+        assert a.size == self.N and b.size == self.N
+        self._check(self._L.mbt_set_transverse_particles(
+            self._h, int(bunch), C.c_void_p(a.ctypes.data), C.c_void_p(b.ctypes.data),
+            _abi.MBT_HOST))
+
+    def get_transverse_particles(self, bunch):
+        x = np.empty(self.N)
+        xp = np.empty(self.N)
+        self._check(self._L.mbt_get_transverse_particles(
+            self._h, int(bunch), C.c_void_p(x.ctypes.data), C.c_void_p(xp.ctypes.data),
+            _abi.MBT_HOST))
+        return x, xp
+
+    def track2(self, nturns, profiles_stride=0):
+        """Track nturns; returns (moments [T][M][4], transverse moments
+        [T][M][4] = mean x, mean x', rms x, rms x') (and profiles)."""
+        mom = np.zeros((nturns, self.M, 4))
+        tmom = np.zeros((nturns, self.M, 4))
+        counts = None
+        if profiles_stride:
+            rows = -(-nturns // profiles_stride)
+            counts = np.zeros((rows, self.M, self.nbins), dtype=np.uint32)
+        self._check(self._L.mbt_track2(
+            self._h, int(nturns), C.c_void_p(mom.ctypes.data), C.c_void_p(tmom.ctypes.data),
+            None if counts is None else C.c_void_p(counts.ctypes.data), int(profiles_stride)))
+        return (mom, tmom, counts) if profiles_stride else (mom, tmom)
+
+    def get_rw_history(self):
+        H = np.zeros((self.rw_turns, self.M))
+        self._check(self._L.mbt_get_rw_history(self._h, C.c_void_p(H.ctypes.data)))
+        return H
+
+    def set_rw_history(self, H):
+        a = np.ascontiguousarray(H, dtype=np.float64)
+        assert a.size == self.rw_turns * self.M
+        self._check(self._L.mbt_set_rw_history(self._h, C.c_void_p(a.ctypes.data)))
 
     def query_bytes(self, N):
         sb, wb = C.c_size_t(), C.c_size_t()

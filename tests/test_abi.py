@@ -136,6 +136,47 @@ def test_static_bind_rejects_before_device_work():
     L.mbt_destroy(h)
 
 
+def test_transverse_setters_validate_on_the_host():
+    """The transverse plane's setters reject bad values and wrong call order,
+    the plane doubles the state, and it excludes the matrix-core wakes."""
+    L, h, rc = _ctx()
+    T = _abi.Transverse
+    good = T(18.2, 2.5, -0.7, 7.5, 0.12, -0.03, 1e-9, 8e-3)
+    for bad in (T(18.2, 2.5, -0.7, 0.0, 0.12, -0.03, 1e-9, 8e-3),
+                T(18.2, 2.5, -0.7, 7.5, 0.12, -0.03, -1e-9, 8e-3),
+                T(18.2, 2.5, -0.7, 7.5, 0.12, -0.03, 1e-9, 0.0),
+                T(float("nan"), 2.5, -0.7, 7.5, 0.12, -0.03, 1e-9, 8e-3)):
+        assert L.mbt_set_transverse(h, C.byref(bad)) == _abi.MBT_EINVAL
+    b = (C.c_int32 * 2)(0, 5)
+    cur = (C.c_double * 2)(1e-3, 1e-3)
+    assert L.mbt_set_fill(h, 2, b, cur, None) == 0
+    sb0, wb0 = C.c_size_t(), C.c_size_t()
+    assert L.mbt_query_bytes(h, 1000, C.byref(sb0), C.byref(wb0)) == 0
+    assert L.mbt_set_transverse(h, C.byref(good)) == 0
+    sb, wb = C.c_size_t(), C.c_size_t()
+    assert L.mbt_query_bytes(h, 1000, C.byref(sb), C.byref(wb)) == 0
+    assert sb.value == 2 * sb0.value and wb.value > wb0.value
+    assert L.mbt_set_wake_precision(h, _abi.MBT_WAKE_BF16X2) == _abi.MBT_EINVAL
+    assert L.mbt_set_wake_precision(h, _abi.MBT_WAKE_FP64) == 0
+    bad_q = (_abi.Resonator * 1)(_abi.Resonator(1e6, 0.4, 1e10))
+    assert L.mbt_set_transverse_wake(h, 1, bad_q) == _abi.MBT_EINVAL
+    ok_r = (_abi.Resonator * 1)(_abi.Resonator(1e6, 1.0, 1e10))
+    assert L.mbt_set_transverse_wake(h, 1, ok_r) == 0
+    RW = _abi.TransverseRW
+    for bad in (RW(0.01, 5.8e7, 288.0, 0), RW(0.01, 5.8e7, 288.0, 1025), RW(0.0, 5.8e7, 288.0, 4)):
+        assert L.mbt_set_transverse_rw(h, C.byref(bad)) == _abi.MBT_EINVAL
+    assert L.mbt_set_transverse_rw(h, C.byref(RW(0.01, 5.8e7, 288.0, 16))) == 0
+    sb2, wb2 = C.c_size_t(), C.c_size_t()
+    assert L.mbt_query_bytes(h, 1000, C.byref(sb2), C.byref(wb2)) == 0
+    assert wb2.value >= wb.value + 16 * 2 * 8  # the wall's centroid history
+    # calls that need a binding
+    assert L.mbt_init_transverse(h, 1e-9, 0.0) == _abi.MBT_ESTATE
+    assert L.mbt_get_rw_history(h, None) == _abi.MBT_ESTATE
+    assert L.mbt_track2(h, 1, None, None, None, 0) == _abi.MBT_ESTATE
+    assert L.mbt_set_transverse(h, None) == 0
+    L.mbt_destroy(h)
+
+
 def test_hc_flat_fraction_agrees_with_oracle():
     from oracle import ref
     for frac in (0.5, 0.9, 1.0):

@@ -1,0 +1,200 @@
+"""The transverse plane on the GPU against the FP64 oracle, through the C ABI
+(Sec. 2.2 Eqs. 3-5; Sec. 2.3, Eq. 6 second line and the long-range
+resistive wall): matched initial coordinates within 1e-14; all four
+coordinates after one turn from identical input within 1e-12 relative to
+max(|x|, sigma_x), with the wall kick of a given centroid history; moments of
+(tau, delta) and (x, x') over 100 turns within 1e-9; a checkpoint that
+resumes bit for bit; a plane without a grid and a single-particle bunch."""
+import numpy as np
+import pytest
+
+from paper_1809_00391_amd import tracker as tr
+from paper_1809_00391_amd import workloads as wl
+
+from helpers import COORD_RTOL, MOMENT_RTOL, coord_excess, make_oracle, moment_excess
+
+pytestmark = pytest.mark.gpu
+
+# Horizontal plane with dispersion, chromaticity and noise; a broadband
+# transverse resonator (R_s in Ohm/m) and a copper wall remembered for 8 turns.
+PLANE = dict(tune=18.2137, chromaticity=2.5, alpha=-0.7, beta_m=7.5, disp_m=0.12,
+             disp_prime=-0.031, emittance_m=1e-9, tau_damp_s=8e-3)
+TWAKE = [(2e6, 1.0, 1.2e10)]
+TRW = (0.01, 5.8e7, 288.0, 8)
+
+CASE = wl.Workload(
+    name="transverse parity", ring=wl.RING_R480, buckets=(0, 3, 4, 9, 200),
+    currents_A=(1e-3, 2.5e-3, 0.0, 1.5e-3, 4e-3), N=2 * 4096 + 77, turns=100, seed=7,
+    sigma_tau0=20e-12, sigma_delta0=8.6e-4, short_range=(wl.BB,),
+    grid=(200, -150e-12, 150e-12), long_range=(wl.HOM,), hc_flat=(3, 0.9))
+
+
+def print_case(name, **kw):
+    print(f"[gpu case] {name} {kw}", flush=True)
+
+
+def with_plane(sim, rw=TRW, wake=TWAKE, plane=PLANE):
+    sim.set_transverse(plane)
+    if wake is not None:
+        sim.set_transverse_wake(wake)
+    sim.set_transverse_rw(rw)
+    return sim
+
+
+def make_pair(w, rw=TRW, wake=TWAKE, plane=PLANE):
+    o = make_oracle(w, init=False)
+    with_plane(o, rw, wake, plane)
+    o.alloc_particles(w.N, w.seed)
+    g = tr.Tracker(w.ring)
+    if w.hc_flat is not None:
+        g.set_harmonic_cavity(tr.hc_flat_fraction(w.ring, *w.hc_flat))
+    g.set_fill(w.buckets, w.currents_A, w.streams)
+    if w.grid is not None:
+        g.set_short_range(list(w.short_range), w.grid)
+    if w.long_range:
+        g.set_long_range(list(w.long_range))
+    with_plane(g, rw, wake, plane)
+    g.bind(w.N)
+    g.set_state(0, w.seed, None)  # the oracle's particles were allocated with this seed
+    return o, g
+
+
+def same_particles(w, sims, seed=321, offset=2e-4):
+    rng = np.random.default_rng(seed)
+    sx = np.sqrt(PLANE["emittance_m"] * PLANE["beta_m"])
+    sxp = np.sqrt(PLANE["emittance_m"] / PLANE["beta_m"])
+    for b in range(w.M):
+        tau, delta = wl.gaussian_particles(seed + b, w.N, w.sigma_tau0, w.sigma_delta0)
+        x = offset * (b + 1) + sx * rng.standard_normal(w.N)
+        xp = sxp * rng.standard_normal(w.N)
+        for s in sims:
+            s.set_particles(b, tau, delta)
+            s.set_transverse_particles(b, x, xp)
+
+
+def test_init_transverse_matches_oracle(cuda):
+    w = CASE
+    print_case("init_transverse", N=w.N, M=w.M)
+    o, g = make_pair(w)
+    o.init_gaussian(w.N, w.sigma_tau0, w.sigma_delta0, w.seed)
+    g.init_gaussian(w.sigma_tau0, w.sigma_delta0, w.seed)
+    o.init_transverse(1.5e-9, 3e-4)
+    g.init_transverse(1.5e-9, 3e-4)
+    for b in range(w.M):
+        xo, po = o.get_transverse_particles(b)
+        xg, pg = g.get_transverse_particles(b)
+        assert coord_excess(xg, xo) <= 1e-14
+        assert coord_excess(pg, po) <= 1e-14
+
+
+def test_single_turn_all_coordinates(cuda):
+    """Identical particles, a wall history and a start turn on both sides:
+    one turn applies the wall kick, the bins' transverse wake kicks, the
+    rotation, adiabatic damping and noise."""
+    w = CASE
+    print_case("transverse single turn", N=w.N, M=w.M)
+    o, g = make_pair(w)
+    same_particles(w, (o, g))
+    rng = np.random.default_rng(5)
+    H = 1e-4 * rng.standard_normal((TRW[3], w.M))
+    for s in (o, g):
+        s.set_state(5, w.seed, None)
+        s.set_rw_history(H)
+    o.track2(1)
+    g.track2(1)
+    for b in range(w.M):
+        to, do = o.get_particles(b)
+        tg, dg = g.get_particles(b)
+        xo, po = o.get_transverse_particles(b)
+        xg, pg = g.get_transverse_particles(b)
+        for got, want in ((tg, to), (dg, do), (xg, xo), (pg, po)):
+            assert coord_excess(got, want) <= COORD_RTOL, b
+    assert np.array_equal(g.get_rw_history(), o.get_rw_history()) or \
+        np.max(np.abs(g.get_rw_history() - o.get_rw_history())) <= 1e-12 * np.max(np.abs(H))
+
+
+def test_wake_and_wall_change_the_turn(cuda):
+    """The transverse kicks the single-turn test checks are not negligible:
+    without the transverse wake and the wall the oracle's x' after one turn
+    differs by more than 1e-6 of its rms."""
+    w = CASE
+    print_case("transverse kicks matter", N=w.N, M=w.M)
+    o1, _ = make_pair(w)
+    o2 = make_oracle(w, init=False)
+    o2.set_transverse(PLANE)
+    o2.alloc_particles(w.N, w.seed)
+    same_particles(w, (o1, o2))
+    H = 1e-3 * np.ones((TRW[3], w.M))
+    o1.set_state(5, w.seed, None)
+    o2.set_state(5, w.seed, None)
+    o1.set_rw_history(H)
+    o1.track2(1)
+    o2.track2(1)
+    _, p1 = o1.get_transverse_particles(3)
+    _, p2 = o2.get_transverse_particles(3)
+    assert np.max(np.abs(p1 - p2)) > 1e-6 * np.std(p2)
+
+
+def test_moments_over_100_turns(cuda):
+    w = CASE
+    print_case("transverse 100 turns", N=w.N, M=w.M)
+    o, g = make_pair(w)
+    o.init_gaussian(w.N, w.sigma_tau0, w.sigma_delta0, w.seed)
+    g.init_gaussian(w.sigma_tau0, w.sigma_delta0, w.seed)
+    o.init_transverse(1e-9, 5e-4)
+    g.init_transverse(1e-9, 5e-4)
+    mo, to = o.track2(w.turns)
+    mg, tg = g.track2(w.turns)
+    assert moment_excess(mg, mo) <= MOMENT_RTOL
+    assert moment_excess(tg, to) <= MOMENT_RTOL
+    assert np.max(np.abs(g.get_rw_history() - o.get_rw_history())) <= \
+        MOMENT_RTOL * np.max(np.abs(o.get_rw_history()))
+
+
+def test_checkpoint_resumes_bit_for_bit(cuda):
+    w = CASE.with_(N=3001)
+    print_case("transverse checkpoint", N=w.N, M=w.M)
+    _, g = make_pair(w)
+    g.init_gaussian(w.sigma_tau0, w.sigma_delta0, w.seed)
+    g.init_transverse(1e-9, 2e-4)
+    g.track2(20)
+    turn, seed, ph = g.get_state()
+    parts = [g.get_particles(b) + g.get_transverse_particles(b) for b in range(w.M)]
+    H = g.get_rw_history()
+    m_cont, t_cont = g.track2(20)
+    _, h = make_pair(w)
+    for b, (t, d, x, xp) in enumerate(parts):
+        h.set_particles(b, t, d)
+        h.set_transverse_particles(b, x, xp)
+    h.set_state(turn, seed, ph)
+    h.set_rw_history(H)
+    m_res, t_res = h.track2(20)
+    assert np.array_equal(m_cont, m_res)
+    assert np.array_equal(t_cont, t_res)
+    for b in range(w.M):
+        assert np.array_equal(np.concatenate(g.get_transverse_particles(b)),
+                              np.concatenate(h.get_transverse_particles(b)))
+
+
+@pytest.mark.parametrize("N", [1, 3, 700])
+def test_edge_cases(cuda, N):
+    """No grid (no wakes), a single particle, a plane without noise; the wall
+    only."""
+    plane = dict(PLANE, emittance_m=0.0)
+    w = CASE.with_(N=N, grid=None, short_range=(), long_range=(), turns=30)
+    print_case("transverse edge", N=N)
+    o, g = make_pair(w, rw=(0.01, 5.8e7, 288.0, 3), wake=None, plane=plane)
+    same_particles(w, (o, g))
+    mo, to = o.track2(w.turns)
+    mg, tg = g.track2(w.turns)
+    if N == 1:
+        # one particle: the rms values are exactly 0 on both sides; the
+        # means are the coordinates themselves, compared to the largest
+        # value of each coordinate over the run
+        assert np.all(mg[..., 2:] == 0) and np.all(tg[..., 2:] == 0)
+        for got, want in ((mg, mo), (tg, to)):
+            scale = np.max(np.abs(want[..., :2]), axis=(0, 1))
+            assert np.max(np.abs(got[..., :2] - want[..., :2]) / scale) <= MOMENT_RTOL
+        return
+    assert moment_excess(mg, mo) <= MOMENT_RTOL
+    assert moment_excess(tg, to) <= MOMENT_RTOL
