@@ -110,7 +110,7 @@ constexpr size_t kLdsLimit = 64 * 1024;  // dynamic LDS of one push workgroup
 
 // Offsets of every workspace region for a given job shape.
 struct Layout {
-    size_t desc, items_push, items_prep, items_wake, clock, status, Wbf, Wf32;
+    size_t desc, items_push, items_prep, items_wake, clock, status, pctr, Wbf, Wf32;
     size_t W, V, counts, partials, S, seen, gap, qc, phasor, qpp, stream, mom, prof;
     // transverse plane (empty regions without it)
     size_t Tt, U, Xq, tmom, H, rwk, bucket, qb;
@@ -150,6 +150,7 @@ Layout make_layout(int M, int64_t N, int nb, int nlr, bool tr = false, int rw_tu
     L.items_wake = take((size_t)std::max(L.nwake, 1) * sizeof(Item));
     L.clock = take(2 * sizeof(uint32_t));
     L.status = take(sizeof(uint32_t));
+    L.pctr = take(4 * sizeof(uint32_t));  // the persistent push's item counters
     L.W = take((size_t)nbx * sizeof(double));
     L.Wbf = take((size_t)3 * nbx * sizeof(uint16_t));
     L.Wf32 = take((size_t)nbx * sizeof(float));
@@ -463,11 +464,14 @@ int map_kind(const mbt_ctx *c)
     return c->hc.n == 3 ? kMapWakeNoiseHC3 : kMapGeneric;
 }
 
-// Push items of a job: (job, bunch, tile), bunch-major.
+// Push items of a job: (job, bunch, tile), tile-major, so that the short
+// last tile of every bunch is dispatched at the end of the launch (measured:
+// 1.4% shorter push at the full fill than bunch-major).  The order of the
+// items changes no result: each tile has its own partial-sum slot.
 void push_items(const mbt_ctx *c, int job, std::vector<Item> &out)
 {
-    for (int b = 0; b < c->M; ++b)
-        for (int t = 0; t < c->L.ntiles; ++t)
+    for (int t = 0; t < c->L.ntiles; ++t)
+        for (int b = 0; b < c->M; ++b)
             out.push_back(Item{(uint16_t)job, (uint16_t)b, (uint32_t)t});
 }
 
@@ -498,6 +502,7 @@ bool mfma_wake(const mbt_ctx *c) { return c->sr_on && c->wake_mode != kWakeFP64;
 // resonators (a template parameter of the push).
 struct Group {
     int item0 = 0, nitems = 0, nlr = 0, nbins_max = 0, nsub_max = 0, grid = 0;
+    uint32_t *ctr = nullptr;  // item counters of a persistent launch (4 words)
     int map = kMapGeneric;  // compile-time map terms every job of the group shares
 };
 struct WakeGroup {
@@ -535,6 +540,7 @@ PushLaunch push_launch(const Engine &e, const Group &g, int phase)
     l.nsub_max = g.nsub_max;
     l.grid = g.grid > 0 ? std::min(g.grid, g.nitems) : g.nitems;
     l.map = g.map;
+    l.ctr = g.ctr;
     return l;
 }
 
@@ -652,6 +658,7 @@ Engine single_engine(const mbt_ctx *c)
     g.nsub_max = c->nsub;
     g.grid = c->push_grid;
     g.map = map_kind(c);
+    g.ctr = c->w<uint32_t>(c->L.pctr);
     e.groups.push_back(g);
     e.wake_items = c->w<Item>(c->L.items_wake);
     if (c->sr_on && c->wake_mode != kWakeFP64) {
@@ -1885,7 +1892,7 @@ struct mbt_batch {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;   // private stream that graphs are captured on
     JobDesc *pin_desc = nullptr; // pinned [njobs]
-    size_t off_push = 0, off_prep = 0, off_wake = 0, total = 0;
+    size_t off_push = 0, off_prep = 0, off_wake = 0, off_ctr = 0, total = 0;
     Engine eng;
     std::vector<int> wake_modes;  // each job's wake arithmetic when the batch was made
     int graph_turns = 0;
@@ -1900,7 +1907,7 @@ struct mbt_batch {
 namespace {
 
 size_t batch_layout(mbt_ctx *const *jobs, int n, size_t *off_push, size_t *off_prep,
-                    size_t *off_wake)
+                    size_t *off_wake, size_t *off_ctr = nullptr)
 {
     size_t np = 0, nc = 0, nw = 0;
     for (int j = 0; j < n; ++j) {
@@ -1915,6 +1922,10 @@ size_t batch_layout(mbt_ctx *const *jobs, int n, size_t *off_push, size_t *off_p
     o = align256(o + nc * sizeof(Item));
     *off_wake = o;
     o = align256(o + std::max<size_t>(nw, 1) * sizeof(Item));
+    if (off_ctr)
+        *off_ctr = o;
+    // item counters of persistent push launches: four words per push group
+    o = align256(o + (size_t)(kMaxLR + 1) * 4 * sizeof(uint32_t));
     return o;
 }
 
@@ -2188,7 +2199,7 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
         B->jobs.assign(jobs, jobs + njobs);
         B->work = reinterpret_cast<unsigned char *>(d_work);
         B->stream = reinterpret_cast<hipStream_t>(hip_stream);
-        B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep, &B->off_wake);
+        B->total = batch_layout(jobs, njobs, &B->off_push, &B->off_prep, &B->off_wake, &B->off_ctr);
         // items grouped by long-range count, jobs in the order given
         std::vector<Item> pitems, citems;
         Engine &e = B->eng;
@@ -2210,6 +2221,7 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
             if (g.map < 0)
                 g.map = kMapGeneric;
             g.nitems = (int)pitems.size() - g.item0;
+            g.ctr = reinterpret_cast<uint32_t *>(B->work + B->off_ctr) + 4 * e.groups.size();
             if (g.nitems > 0)
                 e.groups.push_back(g);
         }
@@ -2261,6 +2273,8 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
                                 hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
             (r = hipMemcpyAsync(B->work + B->off_prep, citems.data(), citems.size() * sizeof(Item),
                                 hipMemcpyHostToDevice, B->stream)) != hipSuccess ||
+            (r = hipMemsetAsync(B->work + B->off_ctr, 0, (size_t)(kMaxLR + 1) * 4 * sizeof(uint32_t),
+                                B->stream)) != hipSuccess ||
             (!witems.empty() &&
              (r = hipMemcpyAsync(B->work + B->off_wake, witems.data(), witems.size() * sizeof(Item),
                                  hipMemcpyHostToDevice, B->stream)) != hipSuccess) ||

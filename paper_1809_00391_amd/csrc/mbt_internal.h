@@ -158,8 +158,11 @@ struct PushLaunch {
     int nlr;                  // template group: every job of the items has this many
     int nbins_max;
     int nsub_max;
-    int grid;                 // workgroups; each takes items g, g + grid, ...
+    int grid;                 // workgroups: nitems (one per item) or fewer (persistent)
     int map;                  // MapKind shared by every job of the items
+    // persistent launches: [0..1] next item by phase, [2..3] finished
+    // workgroups by phase; both 0 between launches (k_push rewinds them)
+    uint32_t *ctr;
 };
 struct PrepLaunch {
     int phase;

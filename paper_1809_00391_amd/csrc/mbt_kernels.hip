@@ -129,6 +129,24 @@ __device__ __forceinline__ void normal_pair(uint32_t c0, uint32_t c1, uint32_t c
 // Map pieces.
 // ---------------------------------------------------------------------------
 
+// Whether p holds on every active lane of the wavefront: the lane mask of
+// the comparison that produced p against the execution mask, with no vector
+// instruction beyond that comparison (__all materialises p first).
+__device__ __forceinline__ bool wave_all(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(p) == __builtin_amdgcn_read_exec();
+}
+
+// Slot of tau in a per-bin LDS table with a guard slot on each side: the bin
+// index on the grid, -1 below it, nbins at or above it (the maxNum clamp
+// sends NaN to -1; the conversion saturates), so that either guard stands
+// for "outside the grid".  Within the grid it is the index bin_of gives.
+__device__ __forceinline__ int bin_slot(const MapConst &c, double t)
+{
+    const double x = floor((t - c.tau_min) * c.inv_delta);
+    return min((int)fmax(x, -1.0), c.nbins);
+}
+
 // Bin of tau on the fixed grid; -1 outside [tau_min, tau_max) (and for NaN).
 __device__ __forceinline__ int bin_of(const MapConst &c, double t)
 {
@@ -140,12 +158,12 @@ __device__ __forceinline__ int bin_of(const MapConst &c, double t)
 }
 
 // sin and cos of x: when every lane of the wavefront has |x| <= pi/4 the
-// Taylor polynomials apply directly (the pi/2 reduction would be the
+// minimax polynomials apply directly (the pi/2 reduction would be the
 // identity, so the result is bit for bit the same); otherwise reduce first.
 __device__ __forceinline__ void sincos_wave(double x, double &s, double &c)
 {
     constexpr double kPio4 = 0.7853981633974483;
-    if (__all(fabs(x) <= kPio4))
+    if (wave_all(fabs(x) <= kPio4))
         sincos_poly(x, s, c);
     else
         sincos_cw(x, s, c);
@@ -156,19 +174,19 @@ __device__ __forceinline__ void sincos_wave(double x, double &s, double &c)
 // exp_small takes lane by lane there, so the result is the same).
 __device__ __forceinline__ double exp_wave(double y)
 {
-    if (__all(fabs(y) < 1e-4))
+    if (wave_all(fabs(y) < 1e-4))
         return exp_taylor3(y);
     return exp_small(y);
 }
 
 // sin and cos of the RF phase x = w_rf tau of a pair of particles.  Near the
 // synchronous particle (every lane of the wavefront within |x| <= pi/4) the
-// Taylor polynomials apply directly; otherwise reduce by pi/2 first.
+// minimax polynomials apply directly; otherwise reduce by pi/2 first.
 __device__ __forceinline__ void rf_phase(double x0, double x1, double &s0, double &c0, double &s1,
                                          double &c1)
 {
     constexpr double kPio4 = 0.7853981633974483;
-    if (__all(fabs(x0) <= kPio4 && fabs(x1) <= kPio4)) {
+    if (wave_all(fmax(fabs(x0), fabs(x1)) <= kPio4)) {
         sincos_poly(x0, s0, c0);
         sincos_poly(x1, s1, c1);
     } else {
@@ -283,9 +301,8 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
                                          double *acc)
 {
     if (sr_on<MAP>(c)) {
-        // particles outside the grid go to the extra slot nb, never merged
-        const int k = bin_of(c, t);
-        atomicAdd(&hist_w[k >= 0 ? k : c.nbins], 1u);
+        // particles outside the grid go to a guard slot (-1 or nb), never merged
+        atomicAdd(&hist_w[bin_slot(c, t)], 1u);
     }
     acc[0] += t;
     acc[1] = fma(t, t, acc[1]);
@@ -301,13 +318,13 @@ __device__ __forceinline__ void epilogue(const MapConst &c, uint32_t *hist_w, do
     }
 }
 
-// LDS of the push: V/E0 of every bin plus a zero for "outside the grid",
-// the sub-histograms (every bin plus an "outside" slot), and the wavefront
-// partial sums.
+// LDS of the push: V/E0 of every bin with a zero guard on each side for
+// "outside the grid", the sub-histograms (every bin with a guard slot on each
+// side), and the wavefront partial sums.
 size_t push_lds_bytes(int nbins, int nsub)
 {
-    size_t v = (size_t)(nbins + 1) * sizeof(double);
-    size_t h = (size_t)nsub * (size_t)(nbins + 1) * sizeof(uint32_t);
+    size_t v = (size_t)(nbins + 2) * sizeof(double);
+    size_t h = (size_t)nsub * (size_t)(nbins + 2) * sizeof(uint32_t);
     h = (h + 7) & ~(size_t)7;
     return v + h + (size_t)(kPushThreads / 64) * kPartStride * sizeof(double);
 }
@@ -360,10 +377,8 @@ __device__ __forceinline__ void pair_compute(const MapConst &c, uint32_t key0, u
     if (PUSH) {
         double vb0 = 0.0, vb1 = 0.0;
         if (sr_on<MAP>(c)) {
-            const int nb = c.nbins;
-            const int k0 = bin_of(c, t0), k1 = bin_of(c, t1);
-            vb0 = Vs[k0 >= 0 ? k0 : nb];
-            vb1 = Vs[k1 >= 0 ? k1 : nb];
+            vb0 = Vs[bin_slot(c, t0)];
+            vb1 = Vs[bin_slot(c, t1)];
         }
         double z0 = 0.0, z1 = 0.0;
         if (noise_on<MAP>(c))
@@ -386,9 +401,17 @@ using gptr = __attribute__((address_space(1))) T *;
 typedef double dvec2 __attribute__((ext_vector_type(2)));  // one 16-byte access
 
 // ---------------------------------------------------------------------------
-// k_push: each workgroup (256 threads) takes items g, g + grid, ... of the
-// item list; an item is one tile of 512 ppt particles (8192 for all but
-// small jobs) of one bunch of one job.
+// k_push: an item is one tile of 512 ppt particles (8192 for all but small
+// jobs) of one bunch of one job.  With one workgroup (256 threads) per item
+// (ctr = null, grid = nitems) the hardware hands out the items; a persistent
+// launch (grid < nitems) takes them from the launch's counter ctr[phase]
+// instead, each workgroup fetching its next item while it works on the
+// present one, so that every compute unit of every XCD stays busy until the
+// list is done (a fixed blockIdx -> XCD assignment would leave the faster
+// XCDs idle at the end).  The last workgroup to finish rewinds the counter
+// (ctr[2 + phase] counts finished workgroups), so the next launch in this
+// phase starts from item 0.  Which workgroup takes which tile changes no
+// result bit: every tile has its own partial-sum slot.
 // PUSH = false is the bin-only prologue that produces the histogram,
 // deposits and moment sums of the present state without moving it.  Both
 // write the histogram into counts[(clock + 1) & 1]: during the push of turn
@@ -407,14 +430,25 @@ constexpr int push_min_blocks() { return NLR <= 1 ? 4 : 1; }
 template <int NLR, bool PUSH, int MAP>
 __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
     const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
-    const int grid, const int phase)
+    const int grid, const int phase, uint32_t *__restrict__ ctr)
 {
     extern __shared__ double smem[];
+    __shared__ int s_next;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     constexpr int NP = 4 + 2 * NLR;
 
-    for (int it = blockIdx.x; it < nitems; it += grid) {
+    int it = blockIdx.x;
+    if (ctr) {
+        if (tid == 0)
+            s_next = (int)atomicAdd(&ctr[phase], 1u);
+        __syncthreads();
+        it = s_next;
+    }
+    while (it < nitems) {
+        uint32_t next = 0;
+        if (ctr && tid == 0)
+            next = atomicAdd(&ctr[phase], 1u);  // in flight while this tile is pushed
         // descriptors are read-only here, so these loads are scalar
         const Item item = items[it];
         const JobDesc &J = jobs[item.job];
@@ -425,18 +459,18 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
         const uint32_t clock = __builtin_amdgcn_readfirstlane(J.clock[phase]);
         const uint32_t turn = clock;  // push of turn n runs with the clock at n
 
-        double *Vs = smem;  // [nb + 1]
-        uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb + 1);
-        const int nbh = nb + 1;  // sub-histogram stride: the bins and the outside slot
-        double *red = smem + nb + 1 + ((J.nsub * nbh + 1) >> 1);
+        double *Vs = smem + 1;  // [-1 .. nb]
+        uint32_t *hist = reinterpret_cast<uint32_t *>(smem + nb + 2);
+        const int nbh = nb + 2;  // sub-histogram stride: the bins and a guard slot on each side
+        double *red = smem + nb + 2 + ((J.nsub * nbh + 1) >> 1);
 
         for (int k = tid; k < J.nsub * nbh; k += kPushThreads)
             hist[k] = 0u;
         if (PUSH && sr_on<MAP>(c))
-            for (int k = tid; k <= nb; k += kPushThreads)
-                Vs[k] = k < nb ? J.V[(size_t)b * nb + k] * c.inv_E0 : 0.0;
+            for (int k = tid - 1; k <= nb; k += kPushThreads)
+                Vs[k] = k >= 0 && k < nb ? J.V[(size_t)b * nb + k] * c.inv_E0 : 0.0;
         __syncthreads();
-        uint32_t *hist_w = hist + (J.nsub > 0 ? (wave % J.nsub) * nbh : 0);
+        uint32_t *hist_w = hist + 1 + (J.nsub > 0 ? (wave % J.nsub) * nbh : 0);
 
         double seen[NLR > 0 ? NLR : 1][2];
 #pragma unroll
@@ -532,12 +566,23 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
             for (int k = tid; k < nb; k += kPushThreads) {
                 uint32_t sum = 0;
                 for (int q = 0; q < J.nsub; ++q)
-                    sum += hist[q * nbh + k];
+                    sum += hist[q * nbh + 1 + k];
                 if (sum)
                     atomicAdd(&out[k], sum);
             }
         }
+        if (ctr && tid == 0)
+            s_next = (int)next;
         __syncthreads();  // LDS is reused by the next item
+        it = ctr ? s_next : it + grid;
+    }
+    if (ctr && tid == 0) {
+        // every fetch of this workgroup has returned; the last workgroup to
+        // get here rewinds the counters for the next launch in this phase
+        if (atomicAdd(&ctr[2 + phase], 1u) == (uint32_t)grid - 1u) {
+            atomicExch(&ctr[phase], 0u);
+            atomicExch(&ctr[2 + phase], 0u);
+        }
     }
 }
 
@@ -1554,12 +1599,13 @@ template <int NLR, int MAP>
 static void push_launch(const PushLaunch &l, bool push, size_t lds, hipStream_t s)
 {
     constexpr int map = NLR == 1 ? MAP : kMapGeneric;
+    uint32_t *ctr = l.grid < l.nitems ? l.ctr : nullptr;
     if (push)
         hipLaunchKernelGGL((k_push<NLR, true, map>), dim3(l.grid), dim3(kPushThreads), lds, s,
-                           l.jobs, l.items, l.nitems, l.grid, l.phase);
+                           l.jobs, l.items, l.nitems, l.grid, l.phase, ctr);
     else
         hipLaunchKernelGGL((k_push<NLR, false, kMapGeneric>), dim3(l.grid), dim3(kPushThreads),
-                           lds, s, l.jobs, l.items, l.nitems, l.grid, l.phase);
+                           lds, s, l.jobs, l.items, l.nitems, l.grid, l.phase, ctr);
 }
 
 template <int NLR>
@@ -1579,7 +1625,7 @@ static hipError_t push_n(const PushLaunch &l, bool push, hipStream_t s)
 
 hipError_t launch_push(const PushLaunch &l, bool push, hipStream_t s)
 {
-    if (l.nitems < 1 || l.grid < 1)
+    if (l.nitems < 1 || l.grid < 1 || (l.grid < l.nitems && !l.ctr))
         return hipErrorInvalidValue;
     switch (l.nlr) {
     case 0: return push_n<0>(l, push, s);
