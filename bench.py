@@ -12,13 +12,16 @@ bunch: phasor scan; push (kick, damping, noise, drift, histogram, deposits,
 moment sums); between-turn kernel (moments, deposit sums, wake potential);
 moment output.  Inputs are resident in HBM before the timed region.
 
-Two forms, each timed over exactly K turns after W warm-up turns:
+Two forms, both set up first (untimed: the batch's tuner and graph capture,
+as many turns of the plain form), then each timed over exactly K turns after
+W warm-up turns:
   batched_mixed (the `value`): a batch (captured 16-turn HIP graphs, push
       launch shape tuned online during set-up), wake potential as a BF16x2
       Toeplitz product on the matrix cores; FP64 coordinates and phasors;
   plain_fp64: one job per launch set, eager launches, FP64 VALU convolution.
-The roofline of the push kernel comes from further turns whose every launch
-is bracketed by HIP events (outside the timed window).
+Outside the timed windows: a sustained comparison of the two forms (1000
+turns each, twice, interleaved), and the roofline of the push kernel from
+further turns whose every launch is bracketed by HIP events.
 
 Prints one JSON line; progress goes to stderr as each part finishes.
 """
@@ -119,57 +122,126 @@ def push_roofline(push_ms, push_n, particles, copy_gbs, pmc):
     return out
 
 
-def run_form(w, key, form, steps, warmup, roofline_turns, wake, graph_turns, copy_gbs):
-    """Track workload w in one form: set-up, `warmup` untimed turns, exactly
-    `steps` timed turns (HIP events on the stream and the wall clock, the
-    larger counts), then `roofline_turns` turns with every launch bracketed."""
-    import torch
-    from paper_1809_00391_amd import tracker as tr
-    particles = w.M * w.N
-    t = make_tracker(w, wake if form == "batched_mixed" else "fp64")
-    b = None
-    if form == "batched_mixed":
-        b = tr.Batch([t], stream=t.stream, graph_turns=graph_turns, autotune=True)
-        run = lambda n: b.track(n, moments=True)
-        # set-up, untimed: the tuner times its launch-shape candidates on
-        # real turns (two per candidate), then the graph is captured
-        run(64 + 2 * graph_turns)
-    else:
-        run = lambda n: t.track(n, moments=True)
-    if warmup:
-        run(warmup)
-    stream = t.stream
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    mom = run(steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    elapsed = max(wall, ev0.elapsed_time(ev1) / 1e3)
-    m = mom[0] if isinstance(mom, list) else mom
-    res = {"value": particles * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
-           "moments_finite": bool(torch.isfinite(torch.from_numpy(m[-1])).all())}
-    if roofline_turns:
-        timer = b if b is not None else t
+class Form:
+    """One form of the headline workload, set up and warm: the plain FP64
+    tracker (one job per launch set, eager launches, FP64 VALU convolution),
+    or the batched mixed-precision form (a batch: the push launch shape tuned
+    online on real turns, 16-turn HIP graphs, BF16x2 wake on the matrix
+    cores).  Set-up turns are untimed: the batch's tuner candidates and graph
+    capture, and the same number of turns for the plain form, so that both
+    reach their timed window equally warm."""
+
+    def __init__(self, w, key, form, wake, graph_turns):
+        from paper_1809_00391_amd import tracker as tr
+        self.w, self.key, self.form = w, key, form
+        self.wake, self.graph_turns = (wake, graph_turns) if form == "batched_mixed" else ("fp64", 0)
+        self.t = make_tracker(w, self.wake)
+        self.b = None
+        if form == "batched_mixed":
+            self.b = tr.Batch([self.t], stream=self.t.stream, graph_turns=graph_turns, autotune=True)
+            self.run = lambda n: self.b.track(n, moments=True)
+        else:
+            self.run = lambda n: self.t.track(n, moments=True)
+        self.run(64 + 2 * max(graph_turns, 16))
+
+    def timed(self, steps):
+        """Exactly `steps` turns between HIP events on the stream, also timed
+        by the wall clock; returns the larger elapsed time and the moments."""
+        import torch
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        ev0.record(self.t.stream)
+        mom = self.run(steps)
+        ev1.record(self.t.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        return max(wall, ev0.elapsed_time(ev1) / 1e3), (mom[0] if isinstance(mom, list) else mom)
+
+    def roofline(self, turns, copy_gbs):
+        """Push launches of `turns` further turns, each bracketed by HIP
+        events on the tracker's stream (eager launches)."""
+        import torch
+        timer = self.b if self.b is not None else self.t
         timer.set_timing(1)
-        run(roofline_turns)
+        self.run(turns)
         torch.cuda.synchronize()
         push_ms, push_n, btw_ms, btw_n = timer.get_timing()
         timer.set_timing(0)
-        pmc = pmc_record(key, particles)
-        res["push_roofline"] = push_roofline(push_ms, push_n, particles, copy_gbs, pmc)
-        res["between_turn_us"] = btw_ms * 1e3 / btw_n if btw_n else None
-    if b is not None:
-        res.update({"wake": wake, "graph_turns": graph_turns, "autotune": True,
-                    "launch_groups": [list(g) for g in b.launch_info()]})
-        b.close()
-    else:
-        res.update({"wake": "fp64", "graph_turns": 0, "autotune": False})
-    t.close()
-    torch.cuda.empty_cache()
+        particles = self.w.M * self.w.N
+        pmc = pmc_record(self.key, particles)
+        return (push_roofline(push_ms, push_n, particles, copy_gbs, pmc),
+                btw_ms * 1e3 / btw_n if btw_n else None)
+
+    def info(self):
+        d = {"wake": self.wake, "graph_turns": self.graph_turns, "autotune": self.b is not None}
+        if self.b is not None:
+            d["launch_groups"] = [list(g) for g in self.b.launch_info()]
+        return d
+
+    def close(self):
+        import torch
+        if self.b is not None:
+            self.b.close()
+        self.t.close()
+        torch.cuda.empty_cache()
+
+
+def run_forms(w, key, names, steps, warmup, roofline_turns, wake, graph_turns, copy_gbs,
+              sustained_turns):
+    """Both forms set up and warmed first; then each form's `warmup` turns and
+    exactly `steps` timed turns; then, outside the timed windows, a sustained
+    comparison (`sustained_turns` turns of each form, twice, interleaved) and
+    the push roofline of each form."""
+    import torch
+    particles = w.M * w.N
+    forms = {n: Form(w, key, n, wake, graph_turns) for n in names}
+    progress("forms set up: " + ", ".join(names))
+    res = {}
+    for n, f in forms.items():
+        if warmup:
+            f.run(warmup)
+        elapsed, m = f.timed(steps)
+        res[n] = {"value": particles * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+                  "moments_finite": bool(torch.isfinite(torch.from_numpy(m[-1])).all())}
+        progress(f"{n}: {res[n]['value']:.4g} macro-particle-turns/s over {steps} turns")
+    sustained = None
+    if sustained_turns > 0:
+        rates = {n: [] for n in forms}
+        for _ in range(2):
+            for n, f in forms.items():
+                elapsed, _m = f.timed(sustained_turns)
+                rates[n].append(particles * sustained_turns / elapsed)
+        sustained = {"turns": sustained_turns, "repetitions": 2,
+                     "unit": "macro-particle-turns/s",
+                     **{n: max(r) for n, r in rates.items()}}
+        if "batched_mixed" in rates and "plain_fp64" in rates:
+            sustained["batched_over_plain"] = max(rates["batched_mixed"]) / max(rates["plain_fp64"])
+        progress(f"sustained: {sustained}")
+    for n, f in forms.items():
+        if roofline_turns:
+            res[n]["push_roofline"], res[n]["between_turn_us"] = f.roofline(roofline_turns, copy_gbs)
+        res[n].update(f.info())
+        f.close()
+    return res, sustained
+
+
+def cache_resident(turns, roofline_turns, copy_gbs):
+    """The eight-current scan (8 x 1e6 particles, 3rd-harmonic cavity, BB
+    wake on 512 bins) in the plain FP64 tracker.  Its 128 MB of state fits in
+    the 256 MB Infinity Cache, so its push fraction is not an HBM figure."""
+    from paper_1809_00391_amd import workloads as wl
+    w = wl.PRESETS["c2"]
+    f = Form(w, "c2", "plain_fp64", "fp64", 0)
+    f.run(200)
+    elapsed, m = f.timed(turns)
+    res = {"value": w.M * w.N * turns / elapsed, "ms_per_step": elapsed * 1e3 / turns}
+    if roofline_turns:
+        res["push_roofline"], res["between_turn_us"] = f.roofline(roofline_turns, copy_gbs)
+    f.close()
+    res["workload"] = w.name
+    res["note"] = "state 128 MB, inside the 256 MB Infinity Cache: not an HBM measurement"
     return res
 
 
@@ -253,18 +325,6 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / best / 1e9, ok
-
-
-def cache_resident(turns, roofline_turns, copy_gbs):
-    """The eight-current scan (8 x 1e6 particles, 3rd-harmonic cavity, BB
-    wake on 512 bins) in the plain FP64 tracker.  Its 128 MB of state fits in
-    the 256 MB Infinity Cache, so its push fraction is not an HBM figure."""
-    from paper_1809_00391_amd import workloads as wl
-    w = wl.PRESETS["c2"]
-    res = run_form(w, "c2", "plain_fp64", turns, 200, roofline_turns, "fp64", 0, copy_gbs)
-    res["workload"] = w.name
-    res["note"] = "state 128 MB, inside the 256 MB Infinity Cache: not an HBM measurement"
-    return res
 
 
 # Table 4 of the paper: wall time of 20,000 turns of bunches of 1e5
@@ -370,6 +430,8 @@ def main():
     ap.add_argument("--wake", default="bf16x2", choices=["fp32", "bf16x2", "bf16x3"],
                     help="matrix-core wake arithmetic of the batched form")
     ap.add_argument("--graph-turns", type=int, default=16)
+    ap.add_argument("--sustained-turns", type=int, default=1000,
+                    help="turns of each form (twice, interleaved) for the sustained comparison (0: skip)")
     ap.add_argument("--roofline-turns", type=int, default=200,
                     help="turns after the timed window with every push bracketed by HIP events")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
@@ -411,11 +473,9 @@ def main():
         del a, b
     copy_gbs, copy_ok = copy_bandwidth() if args.copy_bw else (None, None)
     progress(f"copy bandwidth {copy_gbs}")
-    forms = {}
-    for form in args.forms.split(","):
-        forms[form] = run_form(w, args.workload, form, args.steps, args.warmup,
-                               args.roofline_turns, args.wake, args.graph_turns, copy_gbs)
-        progress(f"{form}: {forms[form]['value']:.4g} macro-particle-turns/s")
+    forms, sustained = run_forms(w, args.workload, args.forms.split(","), args.steps, args.warmup,
+                                 args.roofline_turns, args.wake, args.graph_turns, copy_gbs,
+                                 args.sustained_turns)
     head = forms.get("batched_mixed") or forms[next(iter(forms))]
     head_form = "batched_mixed" if "batched_mixed" in forms else next(iter(forms))
     particles = w.M * w.N
@@ -450,6 +510,8 @@ def main():
     }
     if "batched_mixed" in forms and "plain_fp64" in forms:
         out["batched_over_plain"] = forms["batched_mixed"]["value"] / forms["plain_fp64"]["value"]
+    if sustained:
+        out["sustained"] = sustained
     out["copy_exact"] = copy_ok
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

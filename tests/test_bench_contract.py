@@ -24,7 +24,7 @@ def test_bench_json_line(cuda):
     r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "64",
                         "--warmup", "8", "--cpu-budget", "1", "--serve-scale", "0.002",
                         "--cache-resident-turns", "16", "--roofline-turns", "20",
-                        "--table4-turns", "4"],
+                        "--table4-turns", "4", "--sustained-turns", "32"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -42,6 +42,7 @@ def test_bench_json_line(cuda):
     assert d["config"]["bunches"] == 484 and d["config"]["form"] == "batched_mixed"
     assert d["value"] == d["forms"]["batched_mixed"]["value"]
     assert d["forms"]["plain_fp64"]["value"] > 0 and d["batched_over_plain"] > 0
+    assert d["sustained"]["turns"] == 32 and d["sustained"]["batched_over_plain"] > 0
     rl = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rl, k

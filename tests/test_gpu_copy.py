@@ -1,7 +1,8 @@
 """The library's streaming copy kernel (mbt_stream_copy), used as the
 achievable-bandwidth yardstick beside the HBM peak: every byte arrives, no
-byte past the range is written, for sizes below one element per thread, with
-a ragged tail, and large enough for the unrolled grid-stride loop."""
+byte past the range is written, for sizes below one 16-byte element per
+thread, with a ragged last workgroup, and large enough for many thousands of
+workgroups (one element per thread, 4 KiB per workgroup)."""
 import pytest
 import torch
 
