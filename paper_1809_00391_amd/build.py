@@ -16,6 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmbt.so")
 SOURCES = [os.path.join(CSRC, "mbt_kernels.hip"), os.path.join(CSRC, "mbt_host.cpp")]
 HEADERS = [os.path.join(CSRC, "mbt_internal.h"), os.path.join(CSRC, "mbt_fastmath.h"),
+           os.path.join(CSRC, "mbt_rw.h"),
            os.path.join(INCLUDE, "mbt.h")]
 ARCH = os.environ.get("MBT_OFFLOAD_ARCH", "gfx950")
 
