@@ -504,7 +504,14 @@ struct Group {
     int item0 = 0, nitems = 0, nlr = 0, nbins_max = 0, nsub_max = 0, grid = 0;
     uint32_t *ctr = nullptr;  // item counters of a persistent launch (4 words)
     int map = kMapGeneric;  // compile-time map terms every job of the group shares
+    bool stream = false;    // non-temporal particle-row accesses (see stream_rows)
 };
+
+// Particle state above which the push streams its rows with the
+// non-temporal hint: the 256 MB Infinity Cache of the MI355X, which holds a
+// smaller state from one turn to the next.
+constexpr size_t kStreamBytes = (size_t)256 << 20;
+bool stream_rows(size_t state_bytes) { return state_bytes > kStreamBytes; }
 struct WakeGroup {
     int item0 = 0, nitems = 0, mode = 0, nbins_max = 0;
 };
@@ -541,6 +548,7 @@ PushLaunch push_launch(const Engine &e, const Group &g, int phase)
     l.grid = g.grid > 0 ? std::min(g.grid, g.nitems) : g.nitems;
     l.map = g.map;
     l.ctr = g.ctr;
+    l.stream = g.stream ? 1 : 0;
     return l;
 }
 
@@ -659,6 +667,7 @@ Engine single_engine(const mbt_ctx *c)
     g.grid = c->push_grid;
     g.map = map_kind(c);
     g.ctr = c->w<uint32_t>(c->L.pctr);
+    g.stream = stream_rows(c->L.state_bytes);
     e.groups.push_back(g);
     e.wake_items = c->w<Item>(c->L.items_wake);
     if (c->sr_on && c->wake_mode != kWakeFP64) {
@@ -2203,11 +2212,16 @@ int mbt_batch_create(mbt_ctx *const *jobs, int32_t njobs, void *d_work, size_t w
         // items grouped by long-range count, jobs in the order given
         std::vector<Item> pitems, citems;
         Engine &e = B->eng;
+        // the batch's whole particle state is what a turn streams
+        size_t state = 0;
+        for (int j = 0; j < njobs; ++j)
+            state += jobs[j]->L.state_bytes;
         for (int nlr = 0; nlr <= kMaxLR; ++nlr) {
             Group g;
             g.item0 = (int)pitems.size();
             g.nlr = nlr;
             g.map = -1;
+            g.stream = stream_rows(state);
             for (int j = 0; j < njobs; ++j) {
                 mbt_ctx *c = jobs[j];
                 if (c->nlr() != nlr)

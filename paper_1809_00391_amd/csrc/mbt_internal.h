@@ -160,6 +160,7 @@ struct PushLaunch {
     int nsub_max;
     int grid;                 // workgroups: nitems (one per item) or fewer (persistent)
     int map;                  // MapKind shared by every job of the items
+    int stream;               // particle rows read and written with the non-temporal hint
     // persistent launches: [0..1] next item by phase, [2..3] finished
     // workgroups by phase; both 0 between launches (k_push rewinds them)
     uint32_t *ctr;

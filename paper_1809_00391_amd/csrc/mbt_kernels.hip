@@ -404,20 +404,28 @@ template <class T>
 using gptr = __attribute__((address_space(1))) T *;
 typedef double dvec2 __attribute__((ext_vector_type(2)));  // one 16-byte access
 
-// Particle rows are streamed: the push reads every coordinate once and
-// writes it once, and nothing reads it again before the next push, so those
-// loads and stores carry the non-temporal hint (on the full fill this made
-// the push 3.5% faster; the hint on the loads alone or on the stores alone
-// changed nothing).
-template <class T>
-__device__ __forceinline__ T ld_stream(const gptr<T> p)
+// Particle-row accesses of the push.  The push reads every coordinate once
+// and writes it once per turn.  When the particle state of the launch is
+// larger than the 256 MB Infinity Cache it cannot stay there between turns,
+// and the loads and stores carry the non-temporal hint (NT = true): on the
+// full fill (774 MB) this made the push 2.5-3.5% faster, with the hint on
+// the loads alone or on the stores alone changing nothing.  A state that
+// fits (the 128 MB current scan) is read back from the cache every turn,
+// and there the hint made the push 14% slower, so it keeps the default.
+template <bool NT, class T>
+__device__ __forceinline__ T ld_row(const gptr<T> p)
 {
-    return __builtin_nontemporal_load(p);
+    if (NT)
+        return __builtin_nontemporal_load(p);
+    return *p;
 }
-template <class T>
-__device__ __forceinline__ void st_stream(gptr<T> p, T v)
+template <bool NT, class T>
+__device__ __forceinline__ void st_row(gptr<T> p, T v)
 {
-    __builtin_nontemporal_store(v, p);
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -447,7 +455,7 @@ __device__ __forceinline__ void st_stream(gptr<T> p, T v)
 template <int NLR>
 constexpr int push_min_blocks() { return NLR <= 1 ? 4 : 1; }
 
-template <int NLR, bool PUSH, int MAP>
+template <int NLR, bool PUSH, int MAP, bool NT>
 __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
     const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
     const int grid, const int phase, uint32_t *__restrict__ ctr)
@@ -511,8 +519,8 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
         const uint32_t pair0 = tile * (uint32_t)(kPushThreads * ppt);
         if ((int64_t)(pair0 + kPushThreads * ppt) * 2 <= J.N) {
             uint32_t p = pair0 + (uint32_t)tid;
-            dvec2 tv = ld_stream(reinterpret_cast<gptr<dvec2>>(tau + 2u * p));
-            dvec2 dv = ld_stream(reinterpret_cast<gptr<dvec2>>(del + 2u * p));
+            dvec2 tv = ld_row<NT>(reinterpret_cast<gptr<dvec2>>(tau + 2u * p));
+            dvec2 dv = ld_row<NT>(reinterpret_cast<gptr<dvec2>>(del + 2u * p));
 #ifndef MBT_PUSH_UNROLL
 #define MBT_PUSH_UNROLL 1
 #endif
@@ -520,15 +528,15 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
             for (int s = 0; s < ppt; ++s) {
                 dvec2 tn = tv, dn = dv;
                 if (s + 1 < ppt) {
-                    tn = ld_stream(reinterpret_cast<gptr<dvec2>>(tau + 2u * (p + kPushThreads)));
-                    dn = ld_stream(reinterpret_cast<gptr<dvec2>>(del + 2u * (p + kPushThreads)));
+                    tn = ld_row<NT>(reinterpret_cast<gptr<dvec2>>(tau + 2u * (p + kPushThreads)));
+                    dn = ld_row<NT>(reinterpret_cast<gptr<dvec2>>(del + 2u * (p + kPushThreads)));
                 }
                 double t0 = tv.x, t1 = tv.y, d0 = dv.x, d1 = dv.y;
                 pair_compute<NLR, PUSH, MAP>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, true,
                                         t0, t1, d0, d1, acc);
                 if (PUSH) {
-                    st_stream(reinterpret_cast<gptr<dvec2>>(tau + 2u * p), dvec2{t0, t1});
-                    st_stream(reinterpret_cast<gptr<dvec2>>(del + 2u * p), dvec2{d0, d1});
+                    st_row<NT>(reinterpret_cast<gptr<dvec2>>(tau + 2u * p), dvec2{t0, t1});
+                    st_row<NT>(reinterpret_cast<gptr<dvec2>>(del + 2u * p), dvec2{d0, d1});
                 }
                 tv = tn;
                 dv = dn;
@@ -545,22 +553,22 @@ __global__ __launch_bounds__(kPushThreads, push_min_blocks<NLR>()) void k_push(
                 const bool two = j0 < n_last;
                 double t0, t1 = 0.0, d0, d1 = 0.0;
                 if (two) {
-                    const dvec2 tv = ld_stream(reinterpret_cast<gptr<dvec2>>(tau + j0));
-                    const dvec2 dv = ld_stream(reinterpret_cast<gptr<dvec2>>(del + j0));
+                    const dvec2 tv = ld_row<NT>(reinterpret_cast<gptr<dvec2>>(tau + j0));
+                    const dvec2 dv = ld_row<NT>(reinterpret_cast<gptr<dvec2>>(del + j0));
                     t0 = tv.x; t1 = tv.y; d0 = dv.x; d1 = dv.y;
                 } else {
-                    t0 = ld_stream(tau + j0);
-                    d0 = ld_stream(del + j0);
+                    t0 = ld_row<NT>(tau + j0);
+                    d0 = ld_row<NT>(del + j0);
                 }
                 pair_compute<NLR, PUSH, MAP>(c, J.key0, J.key1, turn, Vs, seen, hist_w, p, stream, two,
                                         t0, t1, d0, d1, acc);
                 if (PUSH) {
                     if (two) {
-                        st_stream(reinterpret_cast<gptr<dvec2>>(tau + j0), dvec2{t0, t1});
-                        st_stream(reinterpret_cast<gptr<dvec2>>(del + j0), dvec2{d0, d1});
+                        st_row<NT>(reinterpret_cast<gptr<dvec2>>(tau + j0), dvec2{t0, t1});
+                        st_row<NT>(reinterpret_cast<gptr<dvec2>>(del + j0), dvec2{d0, d1});
                     } else {
-                        st_stream(tau + j0, t0);
-                        st_stream(del + j0, d0);
+                        st_row<NT>(tau + j0, t0);
+                        st_row<NT>(del + j0, d0);
                     }
                 }
             }
@@ -1620,12 +1628,16 @@ static void push_launch(const PushLaunch &l, bool push, size_t lds, hipStream_t 
 {
     constexpr int map = NLR == 1 ? MAP : kMapGeneric;
     uint32_t *ctr = l.grid < l.nitems ? l.ctr : nullptr;
-    if (push)
-        hipLaunchKernelGGL((k_push<NLR, true, map>), dim3(l.grid), dim3(kPushThreads), lds, s,
+    if (push && l.stream)
+        hipLaunchKernelGGL((k_push<NLR, true, map, true>), dim3(l.grid), dim3(kPushThreads), lds, s,
                            l.jobs, l.items, l.nitems, l.grid, l.phase, ctr);
+    else if (push)
+        hipLaunchKernelGGL((k_push<NLR, true, map, false>), dim3(l.grid), dim3(kPushThreads), lds,
+                           s, l.jobs, l.items, l.nitems, l.grid, l.phase, ctr);
     else
-        hipLaunchKernelGGL((k_push<NLR, false, kMapGeneric>), dim3(l.grid), dim3(kPushThreads),
-                           lds, s, l.jobs, l.items, l.nitems, l.grid, l.phase, ctr);
+        hipLaunchKernelGGL((k_push<NLR, false, kMapGeneric, false>), dim3(l.grid),
+                           dim3(kPushThreads), lds, s, l.jobs, l.items, l.nitems, l.grid, l.phase,
+                           ctr);
 }
 
 template <int NLR>
