@@ -245,6 +245,87 @@ def cache_resident(turns, roofline_turns, copy_gbs):
     return res
 
 
+# The physics variants measured on the full fill (the plane and wakes of the
+# transverse GPU parity test, a copper wall, a beam-driven harmonic cavity).
+TRANSVERSE_PLANE = dict(tune=18.2137, chromaticity=2.5, alpha=-0.7, beta_m=7.5, disp_m=0.12,
+                        disp_prime=-0.031, emittance_m=1e-9, tau_damp_s=8e-3)
+TRANSVERSE_WAKE = [(2e6, 1.0, 1.2e10)]     # broadband transverse resonator (Ohm/m, Q, Hz)
+COPPER = (0.01, 5.8e7)                      # pipe radius (m), conductivity (S/m)
+
+
+def physics_variants(turns, copy_gbs):
+    """The full fill (484 bunches x 1e5) with each physics variant of the
+    turn map, in the plain FP64 tracker: throughput over `turns` turns and
+    the push from HIP events over as many more.
+      resistive_wall: the broadband wake plus the short-range wake of a
+        copper pipe (10 mm, the whole ring) in the same wake table, so the
+        same push as the headline;
+      passive_hc: the HOM and a beam-driven third-harmonic resonator as two
+        long-range resonators (the two-resonator push);
+      transverse: one transverse plane with dispersion, chromaticity and
+        noise, a broadband transverse resonator and a copper wall remembered
+        for 8 turns (k_push_tr; 64 B per macro-particle-turn: tau, delta,
+        x and x' read and written)."""
+    import numpy as np
+    import torch
+    from paper_1809_00391_amd import tracker as tr
+    from paper_1809_00391_amd import workloads as wl
+    w = wl.PRESETS["c4"]
+    ring_m = w.ring["harmonic"] * 299792458.0 / w.ring["f_rf_Hz"]
+    out = {}
+    for name in ("resistive_wall", "passive_hc", "transverse"):
+        t = tr.Tracker(w.ring)
+        t.set_fill(w.buckets, w.currents_A, w.streams)
+        t.set_short_range(list(w.short_range), w.grid)
+        lr = list(w.long_range)
+        if name == "passive_hc":
+            lr.append((2.0e3, 2.0e4, 3 * w.ring["f_rf_Hz"] + 0.1e6))
+        t.set_long_range(lr)
+        if name == "resistive_wall":
+            t.set_resistive_wall((COPPER[0], COPPER[1], ring_m))
+        tr_on = name == "transverse"
+        if tr_on:
+            t.set_transverse(TRANSVERSE_PLANE)
+            t.set_transverse_wake(TRANSVERSE_WAKE)
+            t.set_transverse_rw((COPPER[0], COPPER[1], ring_m, 8))
+        t.bind(w.N)
+        t.init_gaussian(w.sigma_tau0, w.sigma_delta0, w.seed)
+        if tr_on:
+            t.init_transverse(TRANSVERSE_PLANE["emittance_m"])
+        run = (lambda n: t.track2(n)[0]) if tr_on else (lambda n: t.track(n))
+        run(50)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        ev0.record(t.stream)
+        m = run(turns)
+        ev1.record(t.stream)
+        torch.cuda.synchronize()
+        elapsed = max(time.perf_counter() - wall0, ev0.elapsed_time(ev1) / 1e3)
+        t.set_timing(1)
+        run(turns)
+        torch.cuda.synchronize()
+        push_ms, push_n, btw_ms, btw_n = t.get_timing()
+        t.set_timing(0)
+        bpp = 64 if tr_on else 32
+        push_s = push_ms / 1e3 / push_n
+        gbs = bpp * w.M * w.N / push_s / 1e9
+        out[name] = {"value": w.M * w.N * turns / elapsed, "ms_per_step": elapsed * 1e3 / turns,
+                     "moments_finite": bool(np.isfinite(m).all()),
+                     "push": {"kernel": "k_push_tr" if tr_on else "k_push", "avg_launch_us": push_s * 1e6,
+                              "bytes_per_particle_turn": bpp, "achieved": gbs, "unit": "GB/s",
+                              "frac": gbs / HBM_PEAK_GBS,
+                              "frac_of_copy": gbs / copy_gbs if copy_gbs else None},
+                     "between_turn_us": btw_ms * 1e3 / btw_n if btw_n else None}
+        t.close()
+        torch.cuda.empty_cache()
+        progress(f"physics variant {name} done")
+    out["workload"] = w.name
+    out["unit"] = "macro-particle-turns/s"
+    return out
+
+
 def cpu_info():
     model = platform.processor() or ""
     try:
@@ -446,6 +527,8 @@ def main():
                     help="admit while the admitted jobs hold fewer particles than this (0: no limit)")
     ap.add_argument("--table4-turns", type=int, default=1000,
                     help="turns of the paper's Table 4 bunch counts (0: skip)")
+    ap.add_argument("--physics-turns", type=int, default=100,
+                    help="turns of each physics variant on the full fill (0: skip)")
     ap.add_argument("--copy-bw", type=int, default=1,
                     help="measure the library copy kernel's bandwidth (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -523,6 +606,8 @@ def main():
     if args.table4_turns > 0:
         out["paper_table4"] = paper_table4(args.table4_turns)
         progress("table 4 done")
+    if args.physics_turns > 0:
+        out["physics_variants"] = physics_variants(args.physics_turns, copy_gbs)
     if args.serve_scale > 0:
         out["serving"] = serving_sample(args.serve_scale, args.serve_budget_gb, args.wake,
                                         args.serve_fill or None)

@@ -24,7 +24,7 @@ def test_bench_json_line(cuda):
     r = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "64",
                         "--warmup", "8", "--cpu-budget", "1", "--serve-scale", "0.002",
                         "--cache-resident-turns", "16", "--roofline-turns", "20",
-                        "--table4-turns", "4", "--sustained-turns", "32"],
+                        "--table4-turns", "4", "--sustained-turns", "32", "--physics-turns", "8"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -55,3 +55,8 @@ def test_bench_json_line(cuda):
     assert d["cache_resident"]["value"] > 0
     assert d["serving"]["batched"]["p99_s"] >= d["serving"]["batched"]["p50_s"]
     assert len(d["paper_table4"]["rows"]) == 7
+    pv = d["physics_variants"]
+    for k in ("resistive_wall", "passive_hc", "transverse"):
+        assert pv[k]["value"] > 0 and pv[k]["moments_finite"], k
+        assert pv[k]["push"]["avg_launch_us"] > 0, k
+    assert pv["transverse"]["push"]["bytes_per_particle_turn"] == 64
