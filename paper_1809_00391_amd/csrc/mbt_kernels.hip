@@ -1213,7 +1213,22 @@ __device__ __forceinline__ void betatron(const TransConst &tc, double din, doubl
     xp = xp2;
 }
 
-template <int NLR, bool PUSH>
+// The four coordinates of a particle pair of the transverse push.
+struct TrRows {
+    dvec2 t, d, x, xp;
+};
+template <bool NT>
+__device__ __forceinline__ TrRows load_tr_rows(const gptr<double> rt, const gptr<double> rd,
+                                               const gptr<double> rx, const gptr<double> rxp,
+                                               uint32_t j0)
+{
+    return TrRows{ld_row<NT>(reinterpret_cast<gptr<dvec2>>(rt + j0)),
+                  ld_row<NT>(reinterpret_cast<gptr<dvec2>>(rd + j0)),
+                  ld_row<NT>(reinterpret_cast<gptr<dvec2>>(rx + j0)),
+                  ld_row<NT>(reinterpret_cast<gptr<dvec2>>(rxp + j0))};
+}
+
+template <int NLR, bool PUSH, bool NT>
 __global__ __launch_bounds__(kPushThreads, 2) void k_push_tr(
     const JobDesc *__restrict__ jobs, const Item *__restrict__ items, const int nitems,
     const int grid, const int phase)
@@ -1275,22 +1290,12 @@ __global__ __launch_bounds__(kPushThreads, 2) void k_push_tr(
         const int ppt = J.ppt;
         const uint32_t pair0 = tile * (uint32_t)(kPushThreads * ppt);
         const uint32_t n_last = (uint32_t)(J.N - 1);
-#pragma unroll 1
-        for (int s = 0; s < ppt; ++s) {
-            const uint32_t p = pair0 + (uint32_t)(s * kPushThreads + tid);
-            const uint32_t j0 = 2u * p;
-            if (j0 > n_last)
-                break;
-            const bool two = j0 < n_last;
-            double t[2], d[2], x[2], xp[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const uint32_t j = i == 0 || two ? j0 + i : j0;
-                t[i] = J.tau[row + j];
-                d[i] = J.delta[row + j];
-                x[i] = J.x[row + j];
-                xp[i] = J.xp[row + j];
-            }
+        const gptr<double> rt = (gptr<double>)(J.tau + row), rd = (gptr<double>)(J.delta + row);
+        const gptr<double> rx = (gptr<double>)(J.x + row), rxp = (gptr<double>)(J.xp + row);
+        // The map and epilogue of the pair (particles j0, j0 + 1; the second
+        // only if `two`), coordinates in place.
+        auto pair = [&](uint32_t p, bool two, double (&t)[2], double (&d)[2], double (&x)[2],
+                        double (&xp)[2]) {
             if (PUSH) {
                 double vb[2] = {0.0, 0.0}, ub[2] = {0.0, 0.0};
                 if (c.sr_on) {
@@ -1343,15 +1348,58 @@ __global__ __launch_bounds__(kPushThreads, 2) void k_push_tr(
                 acc[NP + 2] += xp[i];
                 acc[NP + 3] = fma(xp[i], xp[i], acc[NP + 3]);
             }
-            if (PUSH) {
+        };
+        if ((int64_t)(pair0 + kPushThreads * ppt) * 2 <= J.N) {
+            // full tile: 16-byte pair accesses, the next pair loaded before
+            // the present one is pushed
+            uint32_t p = pair0 + (uint32_t)tid;
+            TrRows cur = load_tr_rows<NT>(rt, rd, rx, rxp, 2u * p);
+#pragma unroll 1
+            for (int s = 0; s < ppt; ++s) {
+                TrRows nxt = cur;
+                if (s + 1 < ppt)
+                    nxt = load_tr_rows<NT>(rt, rd, rx, rxp, 2u * (p + kPushThreads));
+                double t[2] = {cur.t.x, cur.t.y}, d[2] = {cur.d.x, cur.d.y};
+                double x[2] = {cur.x.x, cur.x.y}, xp[2] = {cur.xp.x, cur.xp.y};
+                pair(p, true, t, d, x, xp);
+                if (PUSH) {
+                    const uint32_t j0 = 2u * p;
+                    st_row<NT>(reinterpret_cast<gptr<dvec2>>(rt + j0), dvec2{t[0], t[1]});
+                    st_row<NT>(reinterpret_cast<gptr<dvec2>>(rd + j0), dvec2{d[0], d[1]});
+                    st_row<NT>(reinterpret_cast<gptr<dvec2>>(rx + j0), dvec2{x[0], x[1]});
+                    st_row<NT>(reinterpret_cast<gptr<dvec2>>(rxp + j0), dvec2{xp[0], xp[1]});
+                }
+                cur = nxt;
+                p += kPushThreads;
+            }
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < ppt; ++s) {
+                const uint32_t p = pair0 + (uint32_t)(s * kPushThreads + tid);
+                const uint32_t j0 = 2u * p;
+                if (j0 > n_last)
+                    break;
+                const bool two = j0 < n_last;
+                double t[2], d[2], x[2], xp[2];
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    if (i == 1 && !two)
-                        break;
-                    J.tau[row + j0 + i] = t[i];
-                    J.delta[row + j0 + i] = d[i];
-                    J.x[row + j0 + i] = x[i];
-                    J.xp[row + j0 + i] = xp[i];
+                    const uint32_t j = i == 0 || two ? j0 + i : j0;
+                    t[i] = ld_row<NT>(rt + j);
+                    d[i] = ld_row<NT>(rd + j);
+                    x[i] = ld_row<NT>(rx + j);
+                    xp[i] = ld_row<NT>(rxp + j);
+                }
+                pair(p, two, t, d, x, xp);
+                if (PUSH) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        if (i == 1 && !two)
+                            break;
+                        st_row<NT>(rt + j0 + i, t[i]);
+                        st_row<NT>(rd + j0 + i, d[i]);
+                        st_row<NT>(rx + j0 + i, x[i]);
+                        st_row<NT>(rxp + j0 + i, xp[i]);
+                    }
                 }
             }
         }
@@ -1673,12 +1721,15 @@ template <int NLR>
 static hipError_t push_tr_n(const PushLaunch &l, bool push, hipStream_t s)
 {
     const size_t lds = push_tr_lds_bytes(l.nbins_max, l.nsub_max);
-    if (push)
-        hipLaunchKernelGGL((k_push_tr<NLR, true>), dim3(l.grid), dim3(kPushThreads), lds, s,
+    if (push && l.stream)
+        hipLaunchKernelGGL((k_push_tr<NLR, true, true>), dim3(l.grid), dim3(kPushThreads), lds, s,
+                           l.jobs, l.items, l.nitems, l.grid, l.phase);
+    else if (push)
+        hipLaunchKernelGGL((k_push_tr<NLR, true, false>), dim3(l.grid), dim3(kPushThreads), lds, s,
                            l.jobs, l.items, l.nitems, l.grid, l.phase);
     else
-        hipLaunchKernelGGL((k_push_tr<NLR, false>), dim3(l.grid), dim3(kPushThreads), lds, s,
-                           l.jobs, l.items, l.nitems, l.grid, l.phase);
+        hipLaunchKernelGGL((k_push_tr<NLR, false, false>), dim3(l.grid), dim3(kPushThreads), lds,
+                           s, l.jobs, l.items, l.nitems, l.grid, l.phase);
     return hipGetLastError();
 }
 
