@@ -113,6 +113,37 @@ def test_single_turn_all_coordinates(cuda):
         np.max(np.abs(g.get_rw_history() - o.get_rw_history())) <= 1e-12 * np.max(np.abs(H))
 
 
+# Ninety bunches of 1e5: the push runs full tiles of 8192 particles with the
+# next pair prefetched, each bunch ends in a ragged tile, and the 288 MB of
+# particle state (above the 256 MB Infinity Cache) is streamed.
+FULL_TILES = CASE.with_(name="transverse full tiles", buckets=tuple(range(90)),
+                        currents_A=(1e-3,) * 90, N=100_000)
+
+
+def test_single_turn_full_tiles(cuda):
+    """The single-turn comparison on a fill whose tiles are full-size (16
+    pairs per thread, the prefetching loop) with a ragged last tile per
+    bunch and whose rows are streamed, on three of its bunches."""
+    w = FULL_TILES
+    print_case("transverse single turn, full tiles", N=w.N, M=w.M)
+    o, g = make_pair(w)
+    same_particles(w, (o, g))
+    rng = np.random.default_rng(6)
+    H = 1e-4 * rng.standard_normal((TRW[3], w.M))
+    for s in (o, g):
+        s.set_state(5, w.seed, None)
+        s.set_rw_history(H)
+    o.track2(1)
+    g.track2(1)
+    for b in (0, 17, w.M - 1):
+        to, do = o.get_particles(b)
+        tg, dg = g.get_particles(b)
+        xo, po = o.get_transverse_particles(b)
+        xg, pg = g.get_transverse_particles(b)
+        for got, want in ((tg, to), (dg, do), (xg, xo), (pg, po)):
+            assert coord_excess(got, want) <= COORD_RTOL, b
+
+
 def test_wake_and_wall_change_the_turn(cuda):
     """The transverse kicks the single-turn test checks are not negligible:
     without the transverse wake and the wall the oracle's x' after one turn
