@@ -2048,7 +2048,10 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
             ncand = std::max(ncand, cand[gi].size());
         }
     }
-    const int reps = 2;
+    // every candidate runs `reps` turns, the candidates taken in turn within
+    // each round, so that a drift of the clock over the tuning turns (it
+    // rises over the first turns after idle) favours none of them
+    const int reps = 3;
     if (ncand == 1) {  // all cached
         for (size_t gi = 0; gi < cand.size(); ++gi)
             apply_choice(B, (int)gi, cand[gi][0]);
@@ -2072,12 +2075,12 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
             return 0;
         }
     int64_t used = 0;
-    for (size_t k = 0; k < ncand && !*rc; ++k) {
-        for (size_t gi = 0; gi < cand.size(); ++gi)
-            apply_choice(B, (int)gi, cand[gi][std::min(k, cand[gi].size() - 1)]);
-        if ((*rc = upload_descs(B)))
-            break;
-        for (int r = 0; r < reps && !*rc; ++r, ++used) {
+    for (int r = 0; r < reps && !*rc; ++r) {
+        for (size_t k = 0; k < ncand && !*rc; ++k, ++used) {
+            for (size_t gi = 0; gi < cand.size(); ++gi)
+                apply_choice(B, (int)gi, cand[gi][std::min(k, cand[gi].size() - 1)]);
+            if ((*rc = upload_descs(B)))
+                break;
             if ((*rc = batch_rings(B, t + used, 1, stride)))
                 break;
             const int phase = (int)((t + used) & 1);
@@ -2112,7 +2115,7 @@ int64_t batch_tune(mbt_batch *B, int64_t t, int64_t budget, const int32_t *strid
         for (size_t gi = 0; gi < cand.size(); ++gi) {
             size_t k = std::min_element(best[gi].begin(), best[gi].end()) - best[gi].begin();
             // The default shape (default sub-histograms, one workgroup per
-            // tile) stays unless a candidate beats it by more than 2%: two
+            // tile) stays unless a candidate beats it by more than 2%: three
             // turns per candidate do not resolve smaller differences.
             const Group &g = B->eng.groups[gi];
             const int dsub = g.nbins_max > 0 ? default_nsub(g.nbins_max) : 0;
