@@ -117,8 +117,10 @@ double mbt_ref_resonator_wake(const mbt_ref_resonator *r, double t);
  * 1995): with z = c t, s0 = (2 b^2 / (Z0 sigma))^(1/3),
  *   W = (4 Z0 c L / (pi b^2)) [ exp(-z/s0) cos(sqrt(3) z/s0) / 3
  *        - (sqrt(2)/pi) int_0^inf x^2 exp(-x^2 z/s0) / (x^6 + 8) dx ],
- * so W(0+) = Z0 c L / (pi b^2).  0 for t < 0.  Parity unpinned beyond the
- * tests' closed-form limits and impedance transform. */
+ * so W(0+) = Z0 c L / (pi b^2).  0 for t < 0.  Pinned by W(0+), the
+ * thick-wall z^-3/2 tail and its Fourier transform, which must equal the
+ * round-pipe impedance with DC conductivity at five frequencies spanning
+ * 0.05 to 10 c/s0. */
 double mbt_ref_rw_wake(const mbt_ref_rw *rw, double t);
 
 /* Wake table on a grid: W[0] = sum W(0+)/2, W[k] = sum W(k*Delta), over the

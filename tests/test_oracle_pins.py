@@ -601,7 +601,7 @@ def test_resistive_wall_wake_limits():
     assert ref.rw_wake(RW_CU, -1e-12) == 0.0
 
 
-@pytest.mark.parametrize("kappa", [0.2, 1.0, 3.0])
+@pytest.mark.parametrize("kappa", [0.05, 0.2, 1.0, 3.0, 10.0])
 def test_resistive_wall_wake_transforms_to_impedance(kappa):
     """The Fourier transform of the wake is the round-pipe impedance with DC
     conductivity, Z(w) = (L / (2 pi b)) / (1/Z_s + i w eps0 b / 2) with the
